@@ -1,0 +1,152 @@
+/*
+ * libomm: dense orbital minimization method (OMM) on one AMD Instinct MI355X (gfx950).
+ *
+ * The library minimizes the OMM functional of Corsetti, "The orbital minimization method for
+ * electronic structure calculations with finite-range atomic basis sets" (arXiv:1312.1549):
+ *
+ *     E[C] = 4 Tr{HW} - 2 Tr{SW HW},   HW = C Hs C^T,  SW = C S C^T,  Hs = H - eta S
+ *
+ * (Sec. 2.1, Eq. 8, with the eigenspectrum shift of Sec. 2.2, Eq. 9) by conjugate gradients with
+ * exact quartic line searches (Sec. 2.3, Eqs. 12-16) and the kinetic-energy preconditioner
+ * P = (S + T/tau)^-1 (Sec. 2.4, Eq. 17), stopping on the relative energy change (Sec. 2.5.2,
+ * Eq. 18, taken with absolute values).
+ *
+ * Conventions shared by every entry point:
+ *  - All matrices are FP64, row-major, dense. H, S, T are N x N and symmetric. C is M x N with
+ *    one row per Wannier function (the paper's m x n column matrix C^mu_i holds the same
+ *    numbers), so N = number of basis orbitals (the paper's m), M = number of Wannier functions
+ *    (the paper's n), 0 < M <= N.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device memory on the
+ *    context's device. Host inputs are copied in; device inputs are read during the call only
+ *    (stream-ordered on the context's stream). Outputs go to caller-allocated buffers.
+ *  - A context owns all of its device memory; it is not thread-safe; one context uses one
+ *    HIP stream.
+ *  - Return value: 0 = OMM_OK, > 0 warning, < 0 error. omm_last_error() returns the message of
+ *    the last non-zero status of that context.
+ */
+#ifndef OMM_H_
+#define OMM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  OMM_OK = 0,
+  OMM_W_MAXITER = 1,      /* max_iter line searches done without meeting tol */
+  OMM_E_ARG = -1,         /* invalid argument (sizes, null pointers, tol < 0, missing T, ...) */
+  OMM_E_STATE = -2,       /* call out of order (no H/S yet, no C to resume from, ...) */
+  OMM_E_ALLOC = -3,       /* device allocation failed */
+  OMM_E_HIP = -4,         /* HIP runtime error */
+  OMM_E_NONFINITE = -5,   /* NaN/Inf in an input or in the iteration */
+  OMM_E_PRECON = -6,      /* S + T/tau (or S) could not be inverted */
+  OMM_E_NO_LINE_MIN = -7, /* the quartic along D has no local minimum (Sec. 2.2: eta too low) */
+  OMM_E_DIVERGED = -8,    /* Tr SW exceeded 16 M: the iterate left the basin of the minimum */
+  OMM_E_ASYMMETRIC = -9   /* H, S or T is not symmetric */
+};
+
+/* Arithmetic of the cubic-scaling products (the trace reductions, quartic coefficients and line
+ * minimum are always FP64). */
+enum {
+  OMM_FP64 = 0,   /* FP64 MFMA, FP64 storage */
+  OMM_FP32 = 1,   /* FP32 MFMA, FP32 storage of the M x N and N x N operands */
+  OMM_BF16X3 = 2  /* BF16 MFMA on hi/lo splits (3 products), FP32 accumulation and storage */
+};
+
+typedef struct omm_ctx omm_ctx;
+
+/* Create a context for N basis orbitals and M Wannier functions (0 < M <= N) on the current
+ * HIP device. *out is set to NULL on failure. */
+int omm_create(int64_t N, int64_t M, omm_ctx **out);
+int omm_destroy(omm_ctx *ctx);
+
+/* Select the arithmetic of the products (OMM_FP64 default). With a mixed mode and
+ * fp64_refine != 0, the mixed-precision minimization is followed by an FP64 refinement: HC, SC,
+ * HW, SW are recomputed in FP64 from C and FP64 CG runs to tol. */
+int omm_set_precision(omm_ctx *ctx, int mode, int fp64_refine);
+
+/* Stopping threshold of the mixed-precision phase (default 1e-9; FP64 refinement then runs to
+ * the tol given to omm_minimize). */
+int omm_set_mixed_tol(omm_ctx *ctx, double tol);
+
+/* Use `hip_stream` (a hipStream_t) for all work; NULL restores the context's own stream. */
+int omm_set_stream(omm_ctx *ctx, void *hip_stream);
+
+/* Hamiltonian, overlap and (nullable) kinetic matrices of the generalized eigenproblem
+ * H c = eps S c (Sec. 2.1, Eq. 1). Host pointers, N*N each, copied in. T is needed only for a
+ * finite tau > 0 (Eq. 17). Checked for finite values and symmetry (relative 1e-10):
+ * OMM_E_NONFINITE / OMM_E_ASYMMETRIC. Invalidates the cached shift and preconditioner. */
+int omm_set_HS(omm_ctx *ctx, const double *H, const double *S, const double *T);
+/* Same with device pointers (copied device-to-device, validated on the device). */
+int omm_set_HS_device(omm_ctx *ctx, const double *dH, const double *dS, const double *dT);
+
+/* CG minimization of Eq. 8 from C0 (host, M*N; NULL resumes from the context's current C).
+ *   eta       eigenspectrum shift (Sec. 2.2); must exceed the M-th eigenvalue for the minimum to
+ *             describe the occupied subspace;
+ *   tau       > 0 finite: P = (S + T/tau)^-1; +INFINITY: P = S^-1; <= 0: no preconditioning
+ *             (Sec. 2.4, Eq. 17). P is factorized once and reused while S, T, tau are unchanged;
+ *   tol       stop when |2 (E_new - E)| <= tol |E_new + E| after a line search (Eq. 18);
+ *   max_iter  maximum number of line searches (per phase in mixed precision).
+ * Returns OMM_OK, OMM_W_MAXITER, or an error. */
+int omm_minimize(omm_ctx *ctx, const double *C0, double eta, double tau, double tol,
+                 int max_iter);
+/* Same with C0 a device pointer (M*N FP64; NULL resumes). */
+int omm_minimize_device(omm_ctx *ctx, const double *dC0, double eta, double tau, double tol,
+                        int max_iter);
+
+/* Functional value (Eq. 8, shifted Hamiltonian) at the current C. The unshifted band energy
+ * is E + 2 M eta. */
+int omm_energy(omm_ctx *ctx, double *E);
+
+/* rho = 2 C^T (2I - SW) C (N*N, host): the derivative of E with respect to H; at the minimum
+ * (SW = I) the density matrix 2 sum_i c_i c_i^T of the occupied subspace (Sec. 2.1). */
+int omm_density(omm_ctx *ctx, double *rho);
+int omm_density_device(omm_ctx *ctx, double *d_rho);
+
+/* EDM = 2 C^T HW C (N*N, host): the energy-density matrix; dE/dS = -EDM - eta rho. */
+int omm_edm(omm_ctx *ctx, double *edm);
+int omm_edm_device(omm_ctx *ctx, double *d_edm);
+
+/* Reverse-mode derivative of E: d_gH = gE * rho and d_gS = gE * (-EDM - eta rho) (device N*N
+ * each, FP64), evaluated at the current C (exact derivatives of the minimum at convergence). */
+int omm_backward_device(omm_ctx *ctx, double gE, double *d_gH, double *d_gS);
+
+/* Current C (host M*N), HW and SW (host M*M each; either may be NULL). */
+int omm_get_C(omm_ctx *ctx, double *C);
+int omm_get_subspace(omm_ctx *ctx, double *HW, double *SW);
+/* Preconditioner of the last minimization (host N*N); OMM_E_STATE if none was used. */
+int omm_get_preconditioner(omm_ctx *ctx, double *P);
+
+/* Line searches of the last minimize call (both phases) and the last relative change. */
+int omm_stats(omm_ctx *ctx, int *iters, double *last_rel_change);
+/* Energies E_0, E_1, ... of the last minimize call (phase 1 then refinement), up to cap. */
+int omm_energy_trace(omm_ctx *ctx, double *buf, int cap, int *n);
+
+const char *omm_last_error(const omm_ctx *ctx);
+
+/* ---- many independent systems of uneven size in one set of launches ----
+ * Every CG stage is one grouped launch over the tiles of all live systems; converged systems
+ * drop out of the tile lists. FP32 MFMA products, FP64 reductions. */
+typedef struct omm_batch omm_batch;
+
+int omm_batch_create(int nsys, const int64_t *N, const int64_t *M, omm_batch **out);
+int omm_batch_destroy(omm_batch *b);
+/* System i: host H, S, T (N_i*N_i each; T nullable as for omm_set_HS). */
+int omm_batch_set_HS(omm_batch *b, int i, const double *H, const double *S, const double *T);
+/* C0[i]: host M_i*N_i start of system i (NULL entry: resume from its current C). eta, tau:
+ * arrays of nsys values. Returns OMM_OK if every system converged, OMM_W_MAXITER if some did
+ * not, or the first error. */
+int omm_batch_minimize(omm_batch *b, const double *const *C0, const double *eta,
+                       const double *tau, double tol, int max_iter);
+int omm_batch_energy(omm_batch *b, double *E /* nsys */);
+int omm_batch_iterations(omm_batch *b, int *iters /* nsys */);
+int omm_batch_get_C(omm_batch *b, int i, double *C /* host M_i*N_i */);
+const char *omm_batch_last_error(const omm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OMM_H_ */

@@ -1,0 +1,767 @@
+// Runtime of one OMM minimization: device buffers, the precision plan, the per-iteration stage
+// sequence and the C-ABI entry points declared in include/omm.h.
+//
+// One CG line search (Sec. 2.3) is this stage sequence on the context's stream:
+//   G  = 8 HC - 4 HW SC - 4 SW HC                 gradient, Eq. 12 (two-segment GEMM + epilogue)
+//   PG = G P                                      preconditioning, Eq. 17 (skipped when P = I)
+//   beta, D = -PG + beta D                        Polak-Ribiere direction
+//   [HD | SD] = D [Hs | S]                        operator products (dominant cost)
+//   [H' S' H'' S''] = D [HC; SC; HD; SD]^T        projections, Eqs. 14-15 (one launch)
+//   alpha_0..4, x                                 quartic coefficients, Eq. 13, and line minimum
+//   C, HC, SC += x (D, HD, SD); HW, SW update     Eq. 16 and footnote
+//   E_new, stopping test                          Eq. 8 and Eq. 18
+// Every scalar stays on the device; the host reads the small state block every few iterations
+// to learn whether the run has stopped (later iterations are launched but return at once).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/omm.h"
+#include "omm_internal.h"
+
+using namespace omm;
+
+namespace {
+
+template <typename T>
+struct Work {
+  T *C = nullptr, *HC = nullptr, *SC = nullptr, *G = nullptr, *Gp = nullptr, *PG = nullptr,
+    *D = nullptr, *HD = nullptr, *SD = nullptr;
+};
+
+template <typename T>
+constexpr int elem_type() {
+  return sizeof(T) == 8 ? T_F64 : T_F32;
+}
+
+}  // namespace
+
+struct omm_ctx {
+  int64_t N = 0, M = 0;
+  int device = 0;
+  int mode = OMM_FP64;
+  int refine = 1;
+  double mixed_tol = 1e-9;
+  hipStream_t own = nullptr, stream = nullptr;
+  std::string err;
+
+  // inputs and derived operators (FP64)
+  double *H = nullptr, *S = nullptr, *T = nullptr, *Hs = nullptr, *P = nullptr;
+  float *Hs32 = nullptr, *S32 = nullptr, *P32 = nullptr;
+  bool have_HS = false, have_T = false;
+  bool hs_valid = false, s32_valid = false;
+  double hs_eta = 0.0;
+  int p_kind = -1;  // -1 not built, 0 identity, 1 S^-1, 2 (S + T/tau)^-1
+  double p_tau = 0.0;
+  bool p32_valid = false, hs32_valid = false;
+
+  Work<double> w64;
+  Work<float> w32;
+  double *HW = nullptr, *SW = nullptr, *H1 = nullptr, *S1 = nullptr, *H2 = nullptr, *S2 = nullptr;
+  double *partials = nullptr, *ws = nullptr;
+  size_t ws_bytes = 0;
+  DevState* st = nullptr;
+  DevState* st_host = nullptr;  // pinned
+  int* flags = nullptr;
+  double* trace = nullptr;
+  int trace_cap = 0;
+  double* nn_scratch = nullptr;  // N x N FP64 (density / EDM / preconditioner work)
+  double* inv_work = nullptr;
+
+  bool have_C = false;
+  int c_prec = OMM_FP64;  // precision in which the current C lives
+  double eta_last = 0.0;
+  int iters = 0, trace_n = 0;
+  double last_rel = 0.0;
+  std::vector<double> trace_host;
+};
+
+namespace {
+
+int fail(omm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, x)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, OMM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+template <typename P>
+int dalloc(omm_ctx* c, P** p, size_t count) {
+  if (*p) return OMM_OK;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(P));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, OMM_E_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return OMM_OK;
+}
+
+template <typename P>
+void dfree(P*& p) {
+  if (p) hipFree(p);
+  p = nullptr;
+}
+
+#define TRY(x)                  \
+  do {                          \
+    int r_ = (x);               \
+    if (r_ != OMM_OK) return r_; \
+  } while (0)
+
+template <typename T>
+int alloc_work(omm_ctx* c, Work<T>& w) {
+  const size_t mn = (size_t)c->M * c->N;
+  TRY(dalloc(c, &w.C, mn));
+  TRY(dalloc(c, &w.HC, mn));
+  TRY(dalloc(c, &w.SC, mn));
+  TRY(dalloc(c, &w.G, mn));
+  TRY(dalloc(c, &w.Gp, mn));
+  TRY(dalloc(c, &w.PG, mn));
+  TRY(dalloc(c, &w.D, mn));
+  TRY(dalloc(c, &w.HD, mn));
+  TRY(dalloc(c, &w.SD, mn));
+  return OMM_OK;
+}
+
+template <typename T>
+void free_work(Work<T>& w) {
+  dfree(w.C); dfree(w.HC); dfree(w.SC); dfree(w.G); dfree(w.Gp); dfree(w.PG); dfree(w.D);
+  dfree(w.HD); dfree(w.SD);
+}
+
+// Tile / split-K choice for one GEMM shape (M x N output, K inner).
+void choose_tiling(GemmDesc& d, int M, int N, int K) {
+  const int cus = 256;
+  const long t128 = (long)((M + 127) / 128) * ((N + 127) / 128);
+  const long t64 = (long)((M + 63) / 64) * ((N + 63) / 64);
+  d.tile = t128 >= cus ? 0 : 1;
+  d.splitk = 1;
+  const long tiles = d.tile == 0 ? t128 : t64;
+  if (tiles < cus && K >= 1024) {
+    int sk = (int)((2 * cus + tiles - 1) / tiles);
+    const int kmax = K / 256;
+    if (sk > kmax) sk = kmax;
+    if (sk > 16) sk = 16;
+    if (sk > 1) d.splitk = sk;
+  }
+}
+
+int gemm(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, const int* done) {
+  const int K = ops[0].K[0] + (ops[0].nseg > 1 ? ops[0].K[1] : 0);
+  choose_tiling(d, ops[0].M, ops[0].N, K);
+  if (d.splitk > 1) {
+    const size_t need = gemm_splitk_ws_bytes(ops, nops, d.splitk);
+    if (need > c->ws_bytes) {
+      dfree(c->ws);
+      c->ws_bytes = 0;
+      TRY(dalloc(c, &c->ws, need / sizeof(double) + 1));
+      c->ws_bytes = need;
+    }
+  }
+  HIPCHK(c, gemm_launch(d, ops, nops, done, c->ws, c->ws_bytes, c->stream));
+  return OMM_OK;
+}
+
+GemmOp make_op(int M, int N, int K, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+               int64_t ldc, double alpha = 1.0, const void* X = nullptr, int64_t ldx = 0,
+               double beta = 0.0) {
+  GemmOp op{};
+  op.M = M; op.N = N; op.nseg = 1;
+  op.A[0] = A; op.lda[0] = lda;
+  op.B[0] = B; op.ldb[0] = ldb;
+  op.K[0] = K;
+  op.C = C; op.ldc = ldc;
+  op.X = X; op.ldx = ldx;
+  op.alpha = alpha; op.beta = beta;
+  return op;
+}
+
+int compute_of(int mode) {
+  return mode == OMM_FP64 ? CF64 : (mode == OMM_FP32 ? CF32 : CBF16X3);
+}
+
+bool host_check(const double* A, int64_t n, bool* finite_ok) {
+  *finite_ok = true;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = i; j < n; ++j) {
+      const double a = A[i * n + j], b = A[j * n + i];
+      if (!std::isfinite(a) || !std::isfinite(b)) {
+        *finite_ok = false;
+        return false;
+      }
+      const double m = fmax(1.0, fmax(fabs(a), fabs(b)));
+      if (!(fabs(a - b) <= 1e-10 * m)) return false;
+    }
+  }
+  return true;
+}
+
+int ensure_inputs(omm_ctx* c) {
+  const size_t nn = (size_t)c->N * c->N;
+  TRY(dalloc(c, &c->H, nn));
+  TRY(dalloc(c, &c->S, nn));
+  return OMM_OK;
+}
+
+void invalidate(omm_ctx* c) {
+  c->hs_valid = false;
+  c->hs32_valid = false;
+  c->s32_valid = false;
+  c->p_kind = -1;
+  c->p32_valid = false;
+}
+
+// Hs = H - eta S (Sec. 2.2, Eq. 9) and, for mixed modes, FP32 copies of Hs and S.
+int prepare_shift(omm_ctx* c, double eta) {
+  const size_t nn = (size_t)c->N * c->N;
+  if (!c->hs_valid || c->hs_eta != eta) {
+    TRY(dalloc(c, &c->Hs, nn));
+    HIPCHK(c, shift_hamiltonian(c->H, c->S, eta, c->Hs, (int64_t)nn, c->stream));
+    c->hs_valid = true;
+    c->hs_eta = eta;
+    c->hs32_valid = false;
+  }
+  if (c->mode != OMM_FP64) {
+    if (!c->hs32_valid) {
+      TRY(dalloc(c, &c->Hs32, nn));
+      HIPCHK(c, convert_f64_f32(c->Hs, c->Hs32, (int64_t)nn, c->stream));
+      c->hs32_valid = true;
+    }
+    if (!c->s32_valid) {
+      TRY(dalloc(c, &c->S32, nn));
+      HIPCHK(c, convert_f64_f32(c->S, c->S32, (int64_t)nn, c->stream));
+      c->s32_valid = true;
+    }
+  }
+  return OMM_OK;
+}
+
+// P = (S + T/tau)^-1, S^-1 or I (Sec. 2.4, Eq. 17), factorized once per (S, T, tau).
+int prepare_precon(omm_ctx* c, double tau) {
+  int kind = !(tau > 0.0) ? 0 : (isinf(tau) ? 1 : 2);
+  if (kind == 2 && !c->have_T)
+    return fail(c, OMM_E_ARG, "a finite tau > 0 needs the kinetic matrix T");
+  const size_t nn = (size_t)c->N * c->N;
+  if (c->p_kind != kind || (kind == 2 && c->p_tau != tau)) {
+    if (kind > 0) {
+      TRY(dalloc(c, &c->P, nn));
+      if (kind == 1) HIPCHK(c, copy_f64(c->S, c->P, (int64_t)nn, c->stream));
+      else HIPCHK(c, axpby_f64(c->S, c->T, c->P, 1.0, 1.0 / tau, (int64_t)nn, c->stream));
+      TRY(dalloc(c, &c->inv_work, invert_work_doubles(c->N)));
+      int bad = 0;
+      HIPCHK(c, invert_in_place(c->P, c->N, c->inv_work, c->stream, &bad));
+      if (bad) {
+        c->p_kind = -1;
+        return fail(c, OMM_E_PRECON, "preconditioner inversion hit a zero or non-finite pivot");
+      }
+      HIPCHK(c, symmetrize(c->P, c->N, c->stream));
+    }
+    c->p_kind = kind;
+    c->p_tau = tau;
+    c->p32_valid = false;
+  }
+  if (kind > 0 && c->mode != OMM_FP64 && !c->p32_valid) {
+    TRY(dalloc(c, &c->P32, nn));
+    HIPCHK(c, convert_f64_f32(c->P, c->P32, (int64_t)nn, c->stream));
+    c->p32_valid = true;
+  }
+  return OMM_OK;
+}
+
+int alloc_common(omm_ctx* c, int max_iter) {
+  const size_t mm = (size_t)c->M * c->M;
+  TRY(dalloc(c, &c->HW, mm));
+  TRY(dalloc(c, &c->SW, mm));
+  TRY(dalloc(c, &c->H1, mm));
+  TRY(dalloc(c, &c->S1, mm));
+  TRY(dalloc(c, &c->H2, mm));
+  TRY(dalloc(c, &c->S2, mm));
+  TRY(dalloc(c, &c->partials, (size_t)RED_BLOCKS * NCOEF));
+  TRY(dalloc(c, &c->st, 1));
+  if (!c->st_host) {
+    if (hipHostMalloc((void**)&c->st_host, sizeof(DevState), 0) != hipSuccess) {
+      c->st_host = nullptr;
+      return fail(c, OMM_E_ALLOC, "hipHostMalloc failed");
+    }
+  }
+  const int need = 2 * (max_iter + 2);
+  if (c->trace_cap < need) {
+    dfree(c->trace);
+    TRY(dalloc(c, &c->trace, (size_t)need));
+    c->trace_cap = need;
+  }
+  return OMM_OK;
+}
+
+// Initial products of a phase (Sec. 2.1, Eqs. 5-6; Sec. 2.3 footnote):
+//   [HC | SC] = C [Hs | S], HW = HC C^T, SW = SC C^T, E_0.
+template <typename T>
+int initial_products(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, double* trace) {
+  const int M = (int)c->M, N = (int)c->N;
+  const int et = elem_type<T>();
+  GemmDesc d{compute, et, et, et, et, KC, RC, 0, 1};
+  GemmOp ops[2] = {make_op(M, N, N, w.C, N, Hs, N, w.HC, N),
+                   make_op(M, N, N, w.C, N, S, N, w.SC, N)};
+  TRY(gemm(c, d, ops, 2, nullptr));
+  GemmDesc d2{compute, et, et, T_F64, T_F64, KC, KC, 0, 1};
+  GemmOp ops2[2] = {make_op(M, M, N, w.HC, N, w.C, N, c->HW, M),
+                    make_op(M, M, N, w.SC, N, w.C, N, c->SW, M)};
+  TRY(gemm(c, d2, ops2, 2, nullptr));
+  HIPCHK(c, energy_init(c->HW, c->SW, M, c->partials, c->st, trace, c->stream));
+  return OMM_OK;
+}
+
+// One line search (the stage sequence in the header comment of this file).
+template <typename T>
+int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S,
+                          const T* P, int k, double* trace) {
+  const int M = (int)c->M, N = (int)c->N;
+  const int64_t mn = (int64_t)M * N;
+  const int et = elem_type<T>();
+  const int* done = &c->st->done;
+  T* G = (k & 1) ? w.Gp : w.G;
+  T* Gprev = (k & 1) ? w.G : w.Gp;
+  // G = 8 HC - 4 HW SC - 4 SW HC
+  {
+    GemmDesc d{compute, T_F64, et, et, et, KC, RC, 0, 1};
+    GemmOp op = make_op(M, N, M, c->HW, M, w.SC, N, G, N, -4.0, w.HC, N, 8.0);
+    op.nseg = 2;
+    op.A[1] = c->SW; op.lda[1] = M;
+    op.B[1] = w.HC; op.ldb[1] = N;
+    op.K[1] = M;
+    TRY(gemm(c, d, &op, 1, done));
+  }
+  T* PG = G;
+  if (P) {
+    GemmDesc d{compute, et, et, et, et, KC, RC, 0, 1};
+    GemmOp op = make_op(M, N, N, G, N, P, N, w.PG, N);
+    TRY(gemm(c, d, &op, 1, done));
+    PG = w.PG;
+  }
+  HIPCHK(c, beta_and_direction<T>(G, PG, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials, c->st,
+                                  c->stream));
+  {
+    GemmDesc d{compute, et, et, et, et, KC, RC, 0, 1};
+    GemmOp ops[2] = {make_op(M, N, N, w.D, N, Hs, N, w.HD, N),
+                     make_op(M, N, N, w.D, N, S, N, w.SD, N)};
+    TRY(gemm(c, d, ops, 2, done));
+  }
+  {
+    GemmDesc d{compute, et, et, T_F64, T_F64, KC, KC, 0, 1};
+    GemmOp ops[4] = {make_op(M, M, N, w.D, N, w.HC, N, c->H1, M),
+                     make_op(M, M, N, w.D, N, w.SC, N, c->S1, M),
+                     make_op(M, M, N, w.D, N, w.HD, N, c->H2, M),
+                     make_op(M, M, N, w.D, N, w.SD, N, c->S2, M)};
+    TRY(gemm(c, d, ops, 4, done));
+  }
+  HIPCHK(c, line_search(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
+                        c->stream));
+  HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, w.SD, mn, c->st, c->stream));
+  HIPCHK(c, update_subspace(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
+                            trace, c->stream));
+  return OMM_OK;
+}
+
+int read_state(omm_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return OMM_OK;
+}
+
+// Runs one CG phase to tol / max_iter. Returns the device `done` code through *done_out.
+template <typename T>
+int run_phase(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, const T* P, double tol,
+              int max_iter, int trace_off, int* iters_out, int* done_out) {
+  DevState init{};
+  init.tol = tol;
+  init.max_iter = max_iter;
+  init.done = 0;
+  init.iter = 0;
+  HIPCHK(c, hipMemcpyAsync(c->st, &init, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  double* trace = c->trace + trace_off;
+  TRY(initial_products<T>(c, w, compute, Hs, S, trace));
+  TRY(read_state(c));
+  if (c->st_host->done == 0 && max_iter <= 0) {
+    *iters_out = 0;
+    *done_out = 2;
+    return OMM_OK;
+  }
+  // Host checks the device state every `check` launches; iterations launched after the stop
+  // return immediately.
+  const int check = c->N >= 4096 ? 2 : 8;
+  for (int k = 0; k < max_iter && c->st_host->done == 0; ++k) {
+    TRY(line_search_iteration<T>(c, w, compute, Hs, S, P, k, trace));
+    if ((k + 1) % check == 0 || k + 1 == max_iter) TRY(read_state(c));
+  }
+  TRY(read_state(c));
+  *iters_out = c->st_host->iter;
+  *done_out = c->st_host->done;
+  return OMM_OK;
+}
+
+int status_of_done(omm_ctx* c, int done) {
+  switch (done) {
+    case 1: return OMM_OK;
+    case 2: return fail(c, OMM_W_MAXITER, "max_iter line searches without meeting tol");
+    case -5: return fail(c, OMM_E_NONFINITE, "non-finite value in the iteration");
+    case -7:
+      return fail(c, OMM_E_NO_LINE_MIN,
+                  "the quartic along the search direction has no local minimum (is eta above "
+                  "the M-th eigenvalue?)");
+    case -8: return fail(c, OMM_E_DIVERGED, "Tr SW exceeded 16 M: the iteration diverged");
+    default: return fail(c, OMM_E_HIP, "unexpected device state");
+  }
+}
+
+int minimize_impl(omm_ctx* c, const double* C0, bool C0_device, double eta, double tau, double tol,
+                  int max_iter) {
+  if (!c) return OMM_E_ARG;
+  if (!c->have_HS) return fail(c, OMM_E_STATE, "omm_set_HS must be called before omm_minimize");
+  if (!(tol >= 0.0) || max_iter < 0 || !std::isfinite(eta) || std::isnan(tau))
+    return fail(c, OMM_E_ARG, "need tol >= 0, max_iter >= 0, finite eta, non-NaN tau");
+  if (!C0 && !c->have_C) return fail(c, OMM_E_STATE, "no C0 given and no C to resume from");
+  const size_t mn = (size_t)c->M * c->N;
+  TRY(alloc_common(c, max_iter));
+  TRY(alloc_work<double>(c, c->w64));
+  if (c->mode != OMM_FP64) TRY(alloc_work<float>(c, c->w32));
+  TRY(prepare_shift(c, eta));
+  TRY(prepare_precon(c, tau));
+  c->eta_last = eta;
+
+  // Load C into the working precision of phase 1.
+  if (C0) {
+    if (C0_device) HIPCHK(c, hipMemcpyAsync(c->w64.C, C0, mn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    else HIPCHK(c, hipMemcpyAsync(c->w64.C, C0, mn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    c->c_prec = OMM_FP64;
+  }
+  if (c->mode != OMM_FP64 && c->c_prec == OMM_FP64)
+    HIPCHK(c, convert_f64_f32(c->w64.C, c->w32.C, (int64_t)mn, c->stream));
+  if (c->mode == OMM_FP64 && c->c_prec != OMM_FP64)
+    HIPCHK(c, convert_f32_f64(c->w32.C, c->w64.C, (int64_t)mn, c->stream));
+  c->have_C = true;
+
+  int iters1 = 0, done1 = 0, iters2 = 0, done2 = 0;
+  c->iters = 0;
+  if (c->mode == OMM_FP64) {
+    TRY(run_phase<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr, tol,
+                          max_iter, 0, &iters1, &done1));
+    c->c_prec = OMM_FP64;
+    c->iters = iters1;
+    c->trace_n = iters1 + 1;
+    c->last_rel = 0.0;
+  } else {
+    const int comp = compute_of(c->mode);
+    const double tol1 = c->refine ? fmax(tol, c->mixed_tol) : tol;
+    TRY(run_phase<float>(c, c->w32, comp, c->Hs32, c->S32, c->p_kind > 0 ? c->P32 : nullptr, tol1,
+                         max_iter, 0, &iters1, &done1));
+    c->c_prec = c->mode;
+    c->iters = iters1;
+    c->trace_n = iters1 + 1;
+    if (done1 < 0) return status_of_done(c, done1);
+    if (c->refine) {
+      HIPCHK(c, convert_f32_f64(c->w32.C, c->w64.C, (int64_t)mn, c->stream));
+      TRY(run_phase<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr, tol,
+                            max_iter, iters1 + 1, &iters2, &done2));
+      c->c_prec = OMM_FP64;
+      c->iters = iters1 + iters2;
+      c->trace_n = iters1 + 1 + iters2 + 1;
+      done1 = done2;
+    }
+  }
+  c->last_rel = c->st_host->rel_change;
+  c->trace_host.assign((size_t)c->trace_n, 0.0);
+  HIPCHK(c, hipMemcpyAsync(c->trace_host.data(), c->trace, c->trace_n * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return status_of_done(c, done1);
+}
+
+// C in FP64 (converting from the mixed-precision working copy if that is where it lives).
+int c64(omm_ctx* c) {
+  if (!c->have_C) return fail(c, OMM_E_STATE, "no minimization has run");
+  if (c->c_prec != OMM_FP64) {
+    HIPCHK(c, convert_f32_f64(c->w32.C, c->w64.C, (int64_t)c->M * c->N, c->stream));
+    c->c_prec = OMM_FP64;
+  }
+  return OMM_OK;
+}
+
+// out = scale * C^T X C-style products: rho = 2 C^T (2I - SW) C, EDM = 2 C^T HW C.
+int ct_x_c(omm_ctx* c, const double* Xmm, double diag_for_identity, bool use_identity,
+           double* out) {
+  TRY(c64(c));
+  const int M = (int)c->M, N = (int)c->N;
+  double* Y = c->H1;  // M x M scratch
+  if (use_identity) HIPCHK(c, identity_minus(Xmm, Y, M, diag_for_identity, 1.0, c->stream));
+  else HIPCHK(c, copy_f64(Xmm, Y, (int64_t)M * M, c->stream));
+  double* Z = c->w64.HD;  // M x N scratch: Z = Y C
+  GemmDesc d{CF64, T_F64, T_F64, T_F64, T_F64, KC, RC, 0, 1};
+  GemmOp op = make_op(M, N, M, Y, M, c->w64.C, N, Z, N);
+  TRY(gemm(c, d, &op, 1, nullptr));
+  // out = 2 C^T Z : A(m, k) = C[k, m] (RC), B(k, n) = Z[k, n] (RC)
+  GemmDesc d2{CF64, T_F64, T_F64, T_F64, T_F64, RC, RC, 0, 1};
+  GemmOp op2 = make_op(N, N, M, c->w64.C, N, Z, N, out, N, 2.0);
+  TRY(gemm(c, d2, &op2, 1, nullptr));
+  return OMM_OK;
+}
+
+int need_minimized(omm_ctx* c) {
+  if (!c->have_C || !c->HW) return fail(c, OMM_E_STATE, "no minimization has run");
+  return OMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int omm_create(int64_t N, int64_t M, omm_ctx** out) {
+  if (!out) return OMM_E_ARG;
+  *out = nullptr;
+  if (N <= 0 || M <= 0 || M > N || N > (int64_t)1 << 30) return OMM_E_ARG;
+  omm_ctx* c = new omm_ctx();
+  c->N = N;
+  c->M = M;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return OMM_E_HIP;
+  }
+  if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return OMM_E_HIP;
+  }
+  c->stream = c->own;
+  *out = c;
+  return OMM_OK;
+}
+
+int omm_destroy(omm_ctx* c) {
+  if (!c) return OMM_E_ARG;
+  hipStreamSynchronize(c->stream);
+  dfree(c->H); dfree(c->S); dfree(c->T); dfree(c->Hs); dfree(c->P);
+  dfree(c->Hs32); dfree(c->S32); dfree(c->P32);
+  free_work(c->w64);
+  free_work(c->w32);
+  dfree(c->HW); dfree(c->SW); dfree(c->H1); dfree(c->S1); dfree(c->H2); dfree(c->S2);
+  dfree(c->partials); dfree(c->ws); dfree(c->st); dfree(c->flags); dfree(c->trace);
+  dfree(c->nn_scratch); dfree(c->inv_work);
+  if (c->st_host) hipHostFree(c->st_host);
+  if (c->own) hipStreamDestroy(c->own);
+  delete c;
+  return OMM_OK;
+}
+
+int omm_set_precision(omm_ctx* c, int mode, int fp64_refine) {
+  if (!c) return OMM_E_ARG;
+  if (mode != OMM_FP64 && mode != OMM_FP32 && mode != OMM_BF16X3)
+    return fail(c, OMM_E_ARG, "unknown precision mode");
+  c->mode = mode;
+  c->refine = fp64_refine ? 1 : 0;
+  return OMM_OK;
+}
+
+int omm_set_mixed_tol(omm_ctx* c, double tol) {
+  if (!c) return OMM_E_ARG;
+  if (!(tol >= 0.0)) return fail(c, OMM_E_ARG, "tol must be >= 0");
+  c->mixed_tol = tol;
+  return OMM_OK;
+}
+
+int omm_set_stream(omm_ctx* c, void* s) {
+  if (!c) return OMM_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->stream = s ? (hipStream_t)s : c->own;
+  return OMM_OK;
+}
+
+int omm_set_HS(omm_ctx* c, const double* H, const double* S, const double* T) {
+  if (!c) return OMM_E_ARG;
+  if (!H || !S) return fail(c, OMM_E_ARG, "H and S are required");
+  const int64_t n = c->N;
+  const double* mats[3] = {H, S, T};
+  const char* names[3] = {"H", "S", "T"};
+  for (int i = 0; i < 3; ++i) {
+    if (!mats[i]) continue;
+    bool fin = true;
+    if (!host_check(mats[i], n, &fin)) {
+      if (!fin) return fail(c, OMM_E_NONFINITE, std::string(names[i]) + " has a non-finite entry");
+      return fail(c, OMM_E_ASYMMETRIC, std::string(names[i]) + " is not symmetric");
+    }
+  }
+  TRY(ensure_inputs(c));
+  const size_t bytes = (size_t)n * n * sizeof(double);
+  HIPCHK(c, hipMemcpyAsync(c->H, H, bytes, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->S, S, bytes, hipMemcpyHostToDevice, c->stream));
+  c->have_T = T != nullptr;
+  if (T) {
+    TRY(dalloc(c, &c->T, (size_t)n * n));
+    HIPCHK(c, hipMemcpyAsync(c->T, T, bytes, hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->have_HS = true;
+  invalidate(c);
+  return OMM_OK;
+}
+
+int omm_set_HS_device(omm_ctx* c, const double* dH, const double* dS, const double* dT) {
+  if (!c) return OMM_E_ARG;
+  if (!dH || !dS) return fail(c, OMM_E_ARG, "H and S are required");
+  const int64_t n = c->N;
+  TRY(ensure_inputs(c));
+  TRY(dalloc(c, &c->flags, 8));
+  const size_t bytes = (size_t)n * n * sizeof(double);
+  HIPCHK(c, hipMemcpyAsync(c->H, dH, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->S, dS, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (dT) {
+    TRY(dalloc(c, &c->T, (size_t)n * n));
+    HIPCHK(c, hipMemcpyAsync(c->T, dT, bytes, hipMemcpyDeviceToDevice, c->stream));
+  }
+  const double* mats[3] = {c->H, c->S, dT ? c->T : nullptr};
+  const char* names[3] = {"H", "S", "T"};
+  for (int i = 0; i < 3; ++i) {
+    if (!mats[i]) continue;
+    int h[2] = {0, 0};
+    HIPCHK(c, hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->stream));
+    HIPCHK(c, validate_symmetric(mats[i], n, 1e-10, c->flags, c->stream));
+    HIPCHK(c, hipMemcpyAsync(h, c->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h[0]) {
+      c->have_HS = false;
+      return fail(c, OMM_E_NONFINITE, std::string(names[i]) + " has a non-finite entry");
+    }
+    if (h[1]) {
+      c->have_HS = false;
+      return fail(c, OMM_E_ASYMMETRIC, std::string(names[i]) + " is not symmetric");
+    }
+  }
+  c->have_T = dT != nullptr;
+  c->have_HS = true;
+  invalidate(c);
+  return OMM_OK;
+}
+
+int omm_minimize(omm_ctx* c, const double* C0, double eta, double tau, double tol, int max_iter) {
+  if (C0 && c) {
+    const int64_t mn = c->M * c->N;
+    for (int64_t i = 0; i < mn; ++i)
+      if (!std::isfinite(C0[i])) return fail(c, OMM_E_NONFINITE, "C0 has a non-finite entry");
+  }
+  return minimize_impl(c, C0, false, eta, tau, tol, max_iter);
+}
+
+int omm_minimize_device(omm_ctx* c, const double* dC0, double eta, double tau, double tol,
+                        int max_iter) {
+  return minimize_impl(c, dC0, true, eta, tau, tol, max_iter);
+}
+
+int omm_energy(omm_ctx* c, double* E) {
+  if (!c || !E) return c ? fail(c, OMM_E_ARG, "E is null") : OMM_E_ARG;
+  TRY(need_minimized(c));
+  *E = c->st_host->E;
+  return OMM_OK;
+}
+
+int omm_density_device(omm_ctx* c, double* d_rho) {
+  if (!c || !d_rho) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  TRY(need_minimized(c));
+  TRY(ct_x_c(c, c->SW, 2.0, true, d_rho));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return OMM_OK;
+}
+
+int omm_edm_device(omm_ctx* c, double* d_edm) {
+  if (!c || !d_edm) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  TRY(need_minimized(c));
+  TRY(ct_x_c(c, c->HW, 0.0, false, d_edm));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return OMM_OK;
+}
+
+static int to_host_nn(omm_ctx* c, double* host, int (*fn)(omm_ctx*, double*)) {
+  TRY(dalloc(c, &c->nn_scratch, (size_t)c->N * c->N));
+  TRY(fn(c, c->nn_scratch));
+  HIPCHK(c, hipMemcpy(host, c->nn_scratch, (size_t)c->N * c->N * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  return OMM_OK;
+}
+
+int omm_density(omm_ctx* c, double* rho) {
+  if (!c || !rho) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  return to_host_nn(c, rho, omm_density_device);
+}
+
+int omm_edm(omm_ctx* c, double* edm) {
+  if (!c || !edm) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  return to_host_nn(c, edm, omm_edm_device);
+}
+
+int omm_backward_device(omm_ctx* c, double gE, double* d_gH, double* d_gS) {
+  if (!c || !d_gH || !d_gS) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  if (d_gH == d_gS) return fail(c, OMM_E_ARG, "d_gH and d_gS must not alias");
+  TRY(need_minimized(c));
+  const int64_t nn = c->N * c->N;
+  TRY(ct_x_c(c, c->SW, 2.0, true, d_gH));   // rho
+  TRY(ct_x_c(c, c->HW, 0.0, false, d_gS));  // EDM
+  HIPCHK(c, axpby_f64(d_gS, d_gH, d_gS, -gE, -gE * c->eta_last, nn, c->stream));
+  HIPCHK(c, scale_f64(d_gH, gE, nn, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return OMM_OK;
+}
+
+int omm_get_C(omm_ctx* c, double* C) {
+  if (!c || !C) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  TRY(c64(c));
+  HIPCHK(c, hipMemcpyAsync(C, c->w64.C, (size_t)c->M * c->N * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return OMM_OK;
+}
+
+int omm_get_subspace(omm_ctx* c, double* HW, double* SW) {
+  if (!c) return OMM_E_ARG;
+  TRY(need_minimized(c));
+  const size_t b = (size_t)c->M * c->M * sizeof(double);
+  if (HW) HIPCHK(c, hipMemcpyAsync(HW, c->HW, b, hipMemcpyDeviceToHost, c->stream));
+  if (SW) HIPCHK(c, hipMemcpyAsync(SW, c->SW, b, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return OMM_OK;
+}
+
+int omm_get_preconditioner(omm_ctx* c, double* P) {
+  if (!c || !P) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  if (c->p_kind <= 0 || !c->P) return fail(c, OMM_E_STATE, "no preconditioner has been built");
+  HIPCHK(c, hipMemcpyAsync(P, c->P, (size_t)c->N * c->N * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return OMM_OK;
+}
+
+int omm_stats(omm_ctx* c, int* iters, double* last_rel) {
+  if (!c) return OMM_E_ARG;
+  if (iters) *iters = c->iters;
+  if (last_rel) *last_rel = c->last_rel;
+  return OMM_OK;
+}
+
+int omm_energy_trace(omm_ctx* c, double* buf, int cap, int* n) {
+  if (!c || (!buf && cap > 0)) return c ? fail(c, OMM_E_ARG, "null buffer") : OMM_E_ARG;
+  const int k = (int)c->trace_host.size() < cap ? (int)c->trace_host.size() : cap;
+  for (int i = 0; i < k; ++i) buf[i] = c->trace_host[i];
+  if (n) *n = (int)c->trace_host.size();
+  return OMM_OK;
+}
+
+const char* omm_last_error(const omm_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal declarations shared by the translation units of libomm (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace omm {
+
+// Device-resident scalars of one minimization. Every iteration kernel reads `done` first and
+// returns at once when it is non-zero, so iterations launched after convergence cost nothing.
+struct DevState {
+  double E;          // functional at the current C
+  double E_prev;     // functional before the last line search
+  double x;          // last line-search step
+  double beta;       // last Polak-Ribiere coefficient
+  double pg_g;       // <PG, G> of the current gradient (denominator of the next beta)
+  double alpha[5];   // last quartic coefficients
+  double rel_change; // |2 (E - E_prev)| / |E + E_prev|
+  double tol;
+  int iter;          // completed line searches
+  int max_iter;
+  int done;          // 0 running, 1 converged, 2 max_iter, <0 error code
+  int pad;
+};
+
+// Operand layout of a GEMM operand X with outer index r (row of A, column of B) and inner k:
+//   KC: element (r, k) at X[r * ld + k]   (k contiguous)
+//   RC: element (r, k) at X[k * ld + r]   (r contiguous)
+enum Layout : int { KC = 0, RC = 1 };
+
+enum Compute : int { CF64 = 0, CF32 = 1, CBF16X3 = 2 };
+
+enum ElemType : int { T_F64 = 0, T_F32 = 1 };
+
+struct GemmOp {
+  int M, N;            // output rows, columns
+  int nseg;            // 1 or 2 summed K segments
+  const void* A[2];
+  const void* B[2];
+  int64_t lda[2], ldb[2];
+  int K[2];
+  void* C;             // output
+  int64_t ldc;
+  const void* X;       // epilogue addend (may alias C), nullable
+  int64_t ldx;
+  double alpha, beta;  // C = alpha * sum_seg A_seg B_seg + beta * X
+};
+
+struct GemmDesc {
+  int compute;         // Compute
+  int ta, tb, tc, tx;  // ElemType of A, B, C, X
+  int la, lb;          // Layout of A, B
+  int tile;            // 0: 128x128 macro tile, 1: 64x64, 2: 128x64 (M x N)
+  int splitk;          // >1: K split across workgroups, partials reduced in FP64 (needs ws)
+};
+
+// Launch up to 4 GEMMs that share a descriptor (one launch; blockIdx.z selects the op).
+// `done` (nullable) makes the launch a no-op when *done != 0. `ws` is FP64 scratch for split-K.
+hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int* done,
+                       double* ws, size_t ws_bytes, hipStream_t s);
+size_t gemm_splitk_ws_bytes(const GemmOp* ops, int nops, int splitk);
+
+// ---- elementwise / reduction kernels (omm_kernels.hip) ----
+// Number of per-block partial sums each reduction writes is at most RED_BLOCKS.
+constexpr int RED_BLOCKS = 1024;
+constexpr int NCOEF = 13;
+
+hipError_t shift_hamiltonian(const double* H, const double* S, double eta, double* Hs, int64_t n,
+                             hipStream_t s);
+hipError_t convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
+hipError_t copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
+hipError_t validate_symmetric(const double* A, int64_t n, double rtol, int* flags, hipStream_t s);
+hipError_t symmetrize(double* A, int64_t n, hipStream_t s);
+
+// Energy of (HW, SW): writes partials then finalizes into st (init = 1: first energy of a run).
+hipError_t energy_init(const double* HW, const double* SW, int M, double* partials, DevState* st,
+                       double* trace, hipStream_t s);
+
+template <typename T>
+hipError_t beta_and_direction(const T* G, const T* PG, const T* Gprev, T* D, int64_t n, int first,
+                              double* partials, DevState* st, hipStream_t s);
+
+hipError_t line_search(const double* HW, const double* SW, const double* H1, const double* S1,
+                       const double* H2, const double* S2, int M, double* partials, DevState* st,
+                       hipStream_t s);
+
+template <typename T>
+hipError_t update_coefficients(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
+                               const DevState* st, hipStream_t s);
+
+hipError_t update_subspace(double* HW, double* SW, const double* H1, const double* S1,
+                           const double* H2, const double* S2, int M, double* partials,
+                           DevState* st, double* trace, hipStream_t s);
+
+hipError_t identity_minus(const double* SW, double* out, int M, double diag, double scale,
+                          hipStream_t s);
+hipError_t axpby_f64(const double* a, const double* b, double* out, double ca, double cb, int64_t n,
+                     hipStream_t s);
+hipError_t scale_f64(double* a, double c, int64_t n, hipStream_t s);
+
+// ---- preconditioner (omm_precon.hip) ----
+// In-place inverse of an n x n matrix by a blocked Gauss-Jordan sweep. Returns hipSuccess and
+// sets *bad (host) to 1 if a pivot block was singular or a non-finite value appeared.
+hipError_t invert_in_place(double* A, int64_t n, double* work, hipStream_t s, int* bad);
+size_t invert_work_doubles(int64_t n);
+
+}  // namespace omm

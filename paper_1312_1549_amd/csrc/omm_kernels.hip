@@ -1,0 +1,546 @@
+// Memory-bound stages of one CG line search (Sec. 2.3 of the paper): FP64 reductions for the
+// Polak-Ribiere coefficient and the quartic coefficients (Eq. 13), the device-side line
+// minimum, and the updates of Eq. 16. All reductions are two-pass with a fixed grid, so a rerun
+// is bitwise identical. The scalar state of a minimization lives in device memory (DevState);
+// no stage needs the host.
+#include <math.h>
+
+#include "omm_internal.h"
+
+namespace omm {
+namespace {
+
+constexpr int NT = 256;
+
+// Sum of `v` over the block (FP64, fixed order). Result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) t += sh[i];
+  return t;
+}
+
+int red_blocks(int64_t n) {
+  int64_t b = (n + NT - 1) / NT;
+  if (b > RED_BLOCKS) b = RED_BLOCKS;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+__global__ void k_shift(const double* H, const double* S, double eta, double* Hs, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    Hs[i] = H[i] - eta * S[i];
+}
+
+template <typename A, typename B>
+__global__ void k_convert(const A* src, B* dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    dst[i] = (B)src[i];
+}
+
+int ew_blocks(int64_t n) {
+  int64_t b = (n + NT - 1) / NT;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// flags[0] |= non-finite entry, flags[1] |= |a_ij - a_ji| > rtol * max(1, |a_ij|, |a_ji|).
+__global__ void k_validate(const double* A, int64_t n, double rtol, int* flags) {
+  __shared__ double t[32][33];
+  const int64_t bi = (int64_t)blockIdx.y * 32, bj = (int64_t)blockIdx.x * 32;
+  if (bj < bi) return;  // upper block triangle (incl. diagonal blocks) covers every pair
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bj + r, j = bi + tx;  // transposed tile (bj, bi)
+    t[r][tx] = (i < n && j < n) ? A[i * n + j] : 0.0;
+  }
+  __syncthreads();
+  int bad_f = 0, bad_s = 0;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi + r, j = bj + tx;
+    if (i < n && j < n) {
+      const double a = A[i * n + j], b = t[tx][r];
+      if (!isfinite(a)) bad_f = 1;
+      const double m = fmax(1.0, fmax(fabs(a), fabs(b)));
+      if (!(fabs(a - b) <= rtol * m)) bad_s = 1;
+    }
+  }
+  if (bad_f) atomicOr(&flags[0], 1);
+  if (bad_s) atomicOr(&flags[1], 1);
+}
+
+// A <- (A + A^T) / 2; one thread per unordered pair.
+__global__ void k_symmetrize(double* A, int64_t n) {
+  __shared__ double t[32][33];
+  const int64_t bi = (int64_t)blockIdx.y * 32, bj = (int64_t)blockIdx.x * 32;
+  if (bj < bi) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // load transposed tile (bj, bi) and this tile (bi, bj); write both halves
+  __shared__ double u[32][33];
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bj + r, j = bi + tx;
+    t[r][tx] = (i < n && j < n) ? A[i * n + j] : 0.0;
+    const int64_t i2 = bi + r, j2 = bj + tx;
+    u[r][tx] = (i2 < n && j2 < n) ? A[i2 * n + j2] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi + r, j = bj + tx;
+    if (i < n && j < n) {
+      if (bi == bj && j < i) continue;  // diagonal block: each pair once (j >= i)
+      const double v = 0.5 * (u[r][tx] + t[tx][r]);
+      A[i * n + j] = v;
+      A[j * n + i] = v;
+    }
+  }
+}
+
+// ---- energy of (HW, SW): Eq. 8 -----------------------------------------------------------------
+__global__ void k_energy_partials(const double* HW, const double* SW, int M, double* partials) {
+  __shared__ double sh[NT / 64];
+  const int64_t n = (int64_t)M * M;
+  double tr = 0.0, f = 0.0, trs = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    const int r = (int)(i / M), c = (int)(i % M);
+    const double h = HW[i], s = SW[i];
+    f += s * h;
+    if (r == c) { tr += h; trs += s; }
+  }
+  double a = block_sum(tr, sh);
+  double b = block_sum(f, sh);
+  double c = block_sum(trs, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 3 + 0] = a;
+    partials[blockIdx.x * 3 + 1] = b;
+    partials[blockIdx.x * 3 + 2] = c;
+  }
+}
+
+__global__ void k_energy_init_final(const double* partials, int nb, DevState* st, double* trace) {
+  if (threadIdx.x != 0) return;
+  double tr = 0.0, f = 0.0;
+  for (int b = 0; b < nb; ++b) { tr += partials[b * 3 + 0]; f += partials[b * 3 + 1]; }
+  const double E = 4.0 * tr - 2.0 * f;
+  st->E = E;
+  st->E_prev = E;
+  if (trace) trace[0] = E;
+  if (!isfinite(E)) st->done = -5;
+}
+
+// ---- Polak-Ribiere coefficient and direction ----------------------------------------------------
+template <typename T>
+__global__ void k_pr_partials(const T* G, const T* PG, const T* Gp, int64_t n, int first,
+                              double* partials, const DevState* st) {
+  if (st->done) return;
+  __shared__ double sh[NT / 64];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    const double pg = (double)PG[i];
+    s1 += pg * (double)G[i];
+    if (!first) s2 += pg * (double)Gp[i];
+  }
+  double a = block_sum(s1, sh);
+  double b = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 2 + 0] = a;
+    partials[blockIdx.x * 2 + 1] = b;
+  }
+}
+
+__global__ void k_pr_final(const double* partials, int nb, int first, DevState* st) {
+  if (threadIdx.x != 0 || st->done) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = 0; b < nb; ++b) { s1 += partials[b * 2]; s2 += partials[b * 2 + 1]; }
+  double beta = 0.0;
+  if (!first) {
+    beta = (s1 - s2) / st->pg_g;
+    if (!isfinite(beta)) beta = 0.0;
+  }
+  st->beta = beta;
+  st->pg_g = s1;
+}
+
+template <typename T>
+__global__ void k_direction(const T* PG, T* D, int64_t n, int first, const DevState* st) {
+  if (st->done) return;
+  const double beta = st->beta;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    const double d = first ? -(double)PG[i] : -(double)PG[i] + beta * (double)D[i];
+    D[i] = (T)d;
+  }
+}
+
+// ---- quartic coefficients (Eq. 13) --------------------------------------------------------------
+// Sums (index order used by the finalizer):
+//  0 Tr HW   1 Tr H'   2 Tr H''
+//  3 <SW,HW> 4 <S',HW> 5 <SW,H'> 6 <S'',HW> 7 <SW,H''> 8 sum S'_ij H'_ji 9 <S',H'>
+//  10 <S'',H'> 11 <S',H''> 12 <S'',H''>
+// With HW, SW, H'', S'' symmetric, Tr{A B} = <A, B> whenever A or B is symmetric; only
+// Tr{S' H'} needs the transposed access.
+__global__ void k_coef_partials(const double* HW, const double* SW, const double* H1,
+                                const double* S1, const double* H2, const double* S2, int M,
+                                double* partials, const DevState* st) {
+  if (st->done) return;
+  __shared__ double t[32][33];
+  __shared__ double sh[NT / 64];
+  double acc[NCOEF];
+#pragma unroll
+  for (int k = 0; k < NCOEF; ++k) acc[k] = 0.0;
+  const int tb = (M + 31) / 32;
+  const int ntiles = tb * tb;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int bi = (tile / tb) * 32, bj = (tile % tb) * 32;
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int i = bj + r, j = bi + tx;
+      t[r][tx] = (i < M && j < M) ? H1[(int64_t)i * M + j] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int i = bi + r, j = bj + tx;
+      if (i < M && j < M) {
+        const int64_t e = (int64_t)i * M + j;
+        const double hw = HW[e], sw = SW[e], h1 = H1[e], s1 = S1[e], h2 = H2[e], s2 = S2[e];
+        const double h1t = t[tx][r];  // H'_ji
+        if (i == j) { acc[0] += hw; acc[1] += h1; acc[2] += h2; }
+        acc[3] += sw * hw;
+        acc[4] += s1 * hw;
+        acc[5] += sw * h1;
+        acc[6] += s2 * hw;
+        acc[7] += sw * h2;
+        acc[8] += s1 * h1t;
+        acc[9] += s1 * h1;
+        acc[10] += s2 * h1;
+        acc[11] += s1 * h2;
+        acc[12] += s2 * h2;
+      }
+    }
+  }
+  for (int k = 0; k < NCOEF; ++k) {
+    const double v = block_sum(acc[k], sh);
+    if (threadIdx.x == 0) partials[blockIdx.x * NCOEF + k] = v;
+  }
+}
+
+// Line minimum of q(x) = sum_k a_k x^k: the first local minimum met going downhill from x = 0
+// (the functional has no lower bound, so the lowest of two minima may lie beyond the basin).
+// Descent side x > 0 if a1 < 0 (x < 0 if a1 > 0; a1 = 0 gives x = 0). Candidates are real roots
+// of q' on that side (closed-form cubic, two Newton steps) with q'' > 0; the smallest |x| wins.
+// a4 (then a3) is dropped when negligible against |a1|+|a2|+|a3|+|a4|.
+__device__ double dq(const double* a, double x) {
+  return a[1] + 2.0 * a[2] * x + 3.0 * a[3] * x * x + 4.0 * a[4] * x * x * x;
+}
+__device__ double d2q(const double* a, double x) {
+  return 2.0 * a[2] + 6.0 * a[3] * x + 12.0 * a[4] * x * x;
+}
+
+__device__ int cubic_roots(double a, double b, double c, double d, double* r) {
+  const double A = b / a, B = c / a, Cc = d / a;
+  const double p = B - A * A / 3.0;
+  const double q = 2.0 * A * A * A / 27.0 - A * B / 3.0 + Cc;
+  const double sh = -A / 3.0;
+  const double disc = (q / 2.0) * (q / 2.0) + (p / 3.0) * (p / 3.0) * (p / 3.0);
+  if (disc > 0.0) {
+    const double u = cbrt(-q / 2.0 - copysign(sqrt(disc), q));
+    r[0] = u - p / (3.0 * u) + sh;
+    return 1;
+  }
+  if (p == 0.0) {
+    r[0] = sh;
+    return 1;
+  }
+  const double m = 2.0 * sqrt(-p / 3.0);
+  const double arg = fmin(1.0, fmax(-1.0, 3.0 * q / (p * m)));
+  const double phi = acos(arg) / 3.0;
+  const double two_pi_3 = 2.0 * M_PI / 3.0;
+  for (int k = 0; k < 3; ++k) r[k] = m * cos(phi - two_pi_3 * k) + sh;
+  return 3;
+}
+
+__device__ int line_minimum(const double* a, double* xout) {
+  if (a[1] == 0.0) { *xout = 0.0; return 1; }
+  const double side = a[1] < 0.0 ? 1.0 : -1.0;
+  const double scale = fabs(a[1]) + fabs(a[2]) + fabs(a[3]) + fabs(a[4]);
+  const double tiny = 1e-14 * scale;
+  double roots[3];
+  int nr = 0;
+  if (fabs(a[4]) > tiny) {
+    nr = cubic_roots(4.0 * a[4], 3.0 * a[3], 2.0 * a[2], a[1], roots);
+  } else if (fabs(a[3]) > tiny) {
+    const double qa = 3.0 * a[3], qb = 2.0 * a[2], qc = a[1];
+    const double disc = qb * qb - 4.0 * qa * qc;
+    if (disc >= 0.0) {
+      const double s = -0.5 * (qb + copysign(sqrt(disc), qb));
+      if (s != 0.0) roots[nr++] = qc / s;
+      roots[nr++] = s / qa;
+    }
+  } else {
+    if (a[2] > 0.0) { *xout = -a[1] / (2.0 * a[2]); return 1; }
+    return 0;
+  }
+  int found = 0;
+  double best = 0.0;
+  for (int k = 0; k < nr; ++k) {
+    double x = roots[k];
+    for (int it = 0; it < 2; ++it) {
+      const double h = d2q(a, x);
+      if (h == 0.0) break;
+      const double step = dq(a, x) / h;
+      if (!isfinite(step)) break;
+      x -= step;
+    }
+    if (!isfinite(x) || side * x <= 0.0 || !(d2q(a, x) > 0.0)) continue;
+    if (!found || fabs(x) < fabs(best)) {
+      best = x;
+      found = 1;
+    }
+  }
+  *xout = best;
+  return found;
+}
+
+__global__ void k_line_final(const double* partials, int nb, DevState* st) {
+  if (threadIdx.x != 0 || st->done) return;
+  double s[NCOEF];
+  for (int k = 0; k < NCOEF; ++k) s[k] = 0.0;
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < NCOEF; ++k) s[k] += partials[b * NCOEF + k];
+  double a[5];
+  a[0] = 4.0 * s[0] - 2.0 * s[3];
+  a[1] = 8.0 * s[1] - 4.0 * s[4] - 4.0 * s[5];
+  a[2] = 4.0 * s[2] - 2.0 * s[6] - 2.0 * s[7] - 4.0 * s[8] - 4.0 * s[9];
+  a[3] = -4.0 * s[10] - 4.0 * s[11];
+  a[4] = -2.0 * s[12];
+  for (int k = 0; k < 5; ++k) st->alpha[k] = a[k];
+  for (int k = 0; k < 5; ++k)
+    if (!isfinite(a[k])) { st->done = -5; return; }
+  double x = 0.0;
+  if (!line_minimum(a, &x)) { st->done = -7; return; }
+  st->x = x;
+}
+
+// ---- updates (Eq. 16 and the footnote of Sec. 2.3) ----------------------------------------------
+template <typename T>
+__global__ void k_update_mn(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
+                            const DevState* st) {
+  if (st->done) return;
+  const double x = st->x;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    C[i] = (T)((double)C[i] + x * (double)D[i]);
+    HC[i] = (T)((double)HC[i] + x * (double)HD[i]);
+    SC[i] = (T)((double)SC[i] + x * (double)SD[i]);
+  }
+}
+
+// HW += x (H' + H'^T) + x^2 H'', SW likewise; partial sums of Tr HW, <SW, HW>, Tr SW.
+__global__ void k_update_mm(double* HW, double* SW, const double* H1, const double* S1,
+                            const double* H2, const double* S2, int M, double* partials,
+                            const DevState* st) {
+  if (st->done) return;
+  __shared__ double th[32][33], ts[32][33];
+  __shared__ double sh[NT / 64];
+  const double x = st->x;
+  double tr = 0.0, f = 0.0, trs = 0.0;
+  const int tb = (M + 31) / 32;
+  const int ntiles = tb * tb;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int bi = (tile / tb) * 32, bj = (tile % tb) * 32;
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int i = bj + r, j = bi + tx;
+      const bool in = i < M && j < M;
+      th[r][tx] = in ? H1[(int64_t)i * M + j] : 0.0;
+      ts[r][tx] = in ? S1[(int64_t)i * M + j] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int i = bi + r, j = bj + tx;
+      if (i < M && j < M) {
+        const int64_t e = (int64_t)i * M + j;
+        const double hw = HW[e] + x * H1[e] + x * th[tx][r] + x * x * H2[e];
+        const double sw = SW[e] + x * S1[e] + x * ts[tx][r] + x * x * S2[e];
+        HW[e] = hw;
+        SW[e] = sw;
+        f += sw * hw;
+        if (i == j) { tr += hw; trs += sw; }
+      }
+    }
+  }
+  const double a = block_sum(tr, sh);
+  const double b = block_sum(f, sh);
+  const double c = block_sum(trs, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 3 + 0] = a;
+    partials[blockIdx.x * 3 + 1] = b;
+    partials[blockIdx.x * 3 + 2] = c;
+  }
+}
+
+__global__ void k_update_final(const double* partials, int nb, int M, DevState* st,
+                               double* trace) {
+  if (threadIdx.x != 0 || st->done) return;
+  double tr = 0.0, f = 0.0, trs = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    tr += partials[b * 3 + 0];
+    f += partials[b * 3 + 1];
+    trs += partials[b * 3 + 2];
+  }
+  const double E_new = 4.0 * tr - 2.0 * f;
+  const double E_old = st->E;
+  const double diff = fabs(2.0 * (E_new - E_old)), sum = fabs(E_new + E_old);
+  st->E_prev = E_old;
+  st->E = E_new;
+  st->iter += 1;
+  st->rel_change = sum > 0.0 ? diff / sum : diff;
+  if (trace) trace[st->iter] = E_new;
+  if (!isfinite(E_new)) { st->done = -5; return; }
+  if (trs > 16.0 * (double)M) { st->done = -8; return; }
+  if (diff <= st->tol * sum) { st->done = 1; return; }
+  if (st->iter >= st->max_iter) st->done = 2;
+}
+
+__global__ void k_identity_minus(const double* SW, double* out, int M, double diag, double scale) {
+  const int64_t n = (int64_t)M * M;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    const int r = (int)(i / M), c = (int)(i % M);
+    out[i] = scale * ((r == c ? diag : 0.0) - SW[i]);
+  }
+}
+
+__global__ void k_axpby(const double* a, const double* b, double* out, double ca, double cb,
+                        int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    out[i] = ca * a[i] + cb * b[i];
+}
+
+__global__ void k_scale(double* a, double c, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    a[i] *= c;
+}
+
+int tile_blocks(int M) {
+  const int tb = (M + 31) / 32;
+  int b = tb * tb;
+  return b > RED_BLOCKS ? RED_BLOCKS : b;
+}
+
+}  // namespace
+
+hipError_t shift_hamiltonian(const double* H, const double* S, double eta, double* Hs, int64_t n,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_shift, dim3(ew_blocks(n)), dim3(NT), 0, s, H, S, eta, Hs, n);
+  return hipGetLastError();
+}
+
+hipError_t convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(ew_blocks(n)), dim3(NT), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(ew_blocks(n)), dim3(NT), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t copy_f64(const double* src, double* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<double, double>), dim3(ew_blocks(n)), dim3(NT), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t validate_symmetric(const double* A, int64_t n, double rtol, int* flags, hipStream_t s) {
+  const int tb = (int)((n + 31) / 32);
+  hipLaunchKernelGGL(k_validate, dim3(tb, tb), dim3(NT), 0, s, A, n, rtol, flags);
+  return hipGetLastError();
+}
+
+hipError_t symmetrize(double* A, int64_t n, hipStream_t s) {
+  const int tb = (int)((n + 31) / 32);
+  hipLaunchKernelGGL(k_symmetrize, dim3(tb, tb), dim3(NT), 0, s, A, n);
+  return hipGetLastError();
+}
+
+hipError_t energy_init(const double* HW, const double* SW, int M, double* partials, DevState* st,
+                       double* trace, hipStream_t s) {
+  const int nb = red_blocks((int64_t)M * M);
+  hipLaunchKernelGGL(k_energy_partials, dim3(nb), dim3(NT), 0, s, HW, SW, M, partials);
+  hipLaunchKernelGGL(k_energy_init_final, dim3(1), dim3(64), 0, s, partials, nb, st, trace);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t beta_and_direction(const T* G, const T* PG, const T* Gprev, T* D, int64_t n, int first,
+                              double* partials, DevState* st, hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_pr_partials<T>, dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first, partials,
+                     st);
+  hipLaunchKernelGGL(k_pr_final, dim3(1), dim3(64), 0, s, partials, nb, first, st);
+  hipLaunchKernelGGL(k_direction<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, n, first, st);
+  return hipGetLastError();
+}
+template hipError_t beta_and_direction<double>(const double*, const double*, const double*,
+                                               double*, int64_t, int, double*, DevState*,
+                                               hipStream_t);
+template hipError_t beta_and_direction<float>(const float*, const float*, const float*, float*,
+                                              int64_t, int, double*, DevState*, hipStream_t);
+
+hipError_t line_search(const double* HW, const double* SW, const double* H1, const double* S1,
+                       const double* H2, const double* S2, int M, double* partials, DevState* st,
+                       hipStream_t s) {
+  const int nb = tile_blocks(M);
+  hipLaunchKernelGGL(k_coef_partials, dim3(nb), dim3(NT), 0, s, HW, SW, H1, S1, H2, S2, M,
+                     partials, st);
+  hipLaunchKernelGGL(k_line_final, dim3(1), dim3(64), 0, s, partials, nb, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t update_coefficients(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
+                               const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_mn<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, C, D, HC, HD, SC, SD, n,
+                     st);
+  return hipGetLastError();
+}
+template hipError_t update_coefficients<double>(double*, const double*, double*, const double*,
+                                                double*, const double*, int64_t, const DevState*,
+                                                hipStream_t);
+template hipError_t update_coefficients<float>(float*, const float*, float*, const float*, float*,
+                                               const float*, int64_t, const DevState*,
+                                               hipStream_t);
+
+hipError_t update_subspace(double* HW, double* SW, const double* H1, const double* S1,
+                           const double* H2, const double* S2, int M, double* partials,
+                           DevState* st, double* trace, hipStream_t s) {
+  const int nb = tile_blocks(M);
+  hipLaunchKernelGGL(k_update_mm, dim3(nb), dim3(NT), 0, s, HW, SW, H1, S1, H2, S2, M, partials,
+                     st);
+  hipLaunchKernelGGL(k_update_final, dim3(1), dim3(64), 0, s, partials, nb, M, st, trace);
+  return hipGetLastError();
+}
+
+hipError_t identity_minus(const double* SW, double* out, int M, double diag, double scale,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_identity_minus, dim3(ew_blocks((int64_t)M * M)), dim3(NT), 0, s, SW, out, M,
+                     diag, scale);
+  return hipGetLastError();
+}
+
+hipError_t axpby_f64(const double* a, const double* b, double* out, double ca, double cb, int64_t n,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(ew_blocks(n)), dim3(NT), 0, s, a, b, out, ca, cb, n);
+  return hipGetLastError();
+}
+
+hipError_t scale_f64(double* a, double c, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(ew_blocks(n)), dim3(NT), 0, s, a, c, n);
+  return hipGetLastError();
+}
+
+}  // namespace omm
