@@ -96,6 +96,13 @@ int omm_minimize(omm_ctx *ctx, const double *C0, double eta, double tau, double 
 int omm_minimize_device(omm_ctx *ctx, const double *dC0, double eta, double tau, double tol,
                         int max_iter);
 
+/* Continue the CG of the last minimization (same precision phase, same direction history) for
+ * up to `count` more line searches, stopping early when Eq. 18 holds for `tol` (tol = 0 never
+ * stops early). No setup work is repeated. Returns OMM_OK (converged), OMM_W_MAXITER (count
+ * line searches done) or an error; OMM_E_STATE if no minimization is active (new H/S invalidate
+ * it). */
+int omm_iterate(omm_ctx *ctx, int count, double tol);
+
 /* Functional value (Eq. 8, shifted Hamiltonian) at the current C. The unshifted band energy
  * is E + 2 M eta. */
 int omm_energy(omm_ctx *ctx, double *E);
@@ -121,8 +128,20 @@ int omm_get_preconditioner(omm_ctx *ctx, double *P);
 
 /* Line searches of the last minimize call (both phases) and the last relative change. */
 int omm_stats(omm_ctx *ctx, int *iters, double *last_rel_change);
+/* Line searches of the last minimize call split by phase: mixed precision, then FP64 (an FP64
+ * run reports all of them as FP64). The energy trace holds mixed_iters + 1 entries of the mixed
+ * phase followed by fp64_iters + 1 entries of the FP64 phase (when both ran). */
+int omm_phase_stats(omm_ctx *ctx, int *mixed_iters, int *fp64_iters);
 /* Energies E_0, E_1, ... of the last minimize call (phase 1 then refinement), up to cap. */
 int omm_energy_trace(omm_ctx *ctx, double *buf, int cap, int *n);
+
+/* Diagnostics: with profiling on, every line search records HIP events on the context's stream
+ * around its 7 stages (gradient GEMM, P GEMM, Polak-Ribiere + direction, [HD|SD] GEMM,
+ * projection GEMM, coefficients + line minimum, updates + energy). Turning it on (or off) resets
+ * the sums. omm_stage_times writes min(cap, 7) accumulated stage times in ms and the number of
+ * profiled line searches, and returns the number of stages (7). */
+int omm_set_profiling(omm_ctx *ctx, int on);
+int omm_stage_times(omm_ctx *ctx, double *ms, int cap, int *iters);
 
 const char *omm_last_error(const omm_ctx *ctx);
 

@@ -254,11 +254,13 @@ class Result:
 
 
 def minimize(H, S, T, C0, eta: float, tau: float, tol: float, max_iter: int,
-             P: Optional[np.ndarray] = None, use_given_P: bool = False) -> Result:
+             P: Optional[np.ndarray] = None, use_given_P: bool = False,
+             callback=None) -> Result:
     """CG minimization of Eq. 8 with exact quartic line searches (Secs. 2.1-2.5).
 
     ``P``/``use_given_P`` let a caller supply the preconditioner (``None`` = identity) instead of
-    building it from (S, T, tau).
+    building it from (S, T, tau). ``callback(k, E)`` (optional) is called after the setup
+    (k = 0) and after every line search; it does not change the arithmetic.
     """
     Hs = shifted_hamiltonian(H, S, eta)
     if not use_given_P:
@@ -267,6 +269,8 @@ def minimize(H, S, T, C0, eta: float, tau: float, tol: float, max_iter: int,
     HC, SC, HW, SW = subspace_operators(C, Hs, S)
     E = functional(HW, SW)
     energies = [E]
+    if callback is not None:
+        callback(0, E)
     xs: List[float] = []
     betas: List[float] = []
     G_prev = PG_prev = D = None
@@ -297,6 +301,8 @@ def minimize(H, S, T, C0, eta: float, tau: float, tol: float, max_iter: int,
         betas.append(beta)
         done = converged(E_new, E, tol)
         E = E_new
+        if callback is not None:
+            callback(len(xs), E)
         G_prev, PG_prev = G, PG
         if done:
             status = "converged"

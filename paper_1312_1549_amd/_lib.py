@@ -23,6 +23,9 @@ PROTOTYPES = {
     "omm_set_HS_device": (ct.c_int, [_vp, _vp, _vp, _vp]),
     "omm_minimize": (ct.c_int, [_vp, _vp, ct.c_double, ct.c_double, ct.c_double, ct.c_int]),
     "omm_minimize_device": (ct.c_int, [_vp, _vp, ct.c_double, ct.c_double, ct.c_double, ct.c_int]),
+    "omm_iterate": (ct.c_int, [_vp, ct.c_int, ct.c_double]),
+    "omm_set_profiling": (ct.c_int, [_vp, ct.c_int]),
+    "omm_stage_times": (ct.c_int, [_vp, _c_double_p, ct.c_int, _c_int_p]),
     "omm_energy": (ct.c_int, [_vp, _c_double_p]),
     "omm_density": (ct.c_int, [_vp, _vp]),
     "omm_density_device": (ct.c_int, [_vp, _vp]),
@@ -33,6 +36,7 @@ PROTOTYPES = {
     "omm_get_subspace": (ct.c_int, [_vp, _vp, _vp]),
     "omm_get_preconditioner": (ct.c_int, [_vp, _vp]),
     "omm_stats": (ct.c_int, [_vp, _c_int_p, _c_double_p]),
+    "omm_phase_stats": (ct.c_int, [_vp, _c_int_p, _c_int_p]),
     "omm_energy_trace": (ct.c_int, [_vp, _c_double_p, ct.c_int, _c_int_p]),
     "omm_last_error": (ct.c_char_p, [_vp]),
     "omm_batch_create": (ct.c_int, [ct.c_int, _c_i64_p, _c_i64_p, ct.POINTER(_vp)]),

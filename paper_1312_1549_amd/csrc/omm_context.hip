@@ -32,6 +32,8 @@ struct Work {
     *D = nullptr, *HD = nullptr, *SD = nullptr;
 };
 
+constexpr int NSTAGE = 7;  // gradient, PG, PR+direction, [HD|SD], projections, line search, updates
+
 template <typename T>
 constexpr int elem_type() {
   return sizeof(T) == 8 ? T_F64 : T_F32;
@@ -73,6 +75,18 @@ struct omm_ctx {
 
   bool have_C = false;
   int c_prec = OMM_FP64;  // precision in which the current C lives
+  // active CG phase (continued by omm_iterate)
+  bool phase_active = false;
+  int phase_prec = OMM_FP64;  // precision of the active phase
+  int phase_k = 0;            // line searches launched in the active phase
+  int trace_off = 0;          // offset of the active phase in the energy trace
+  int iters_before = 0;       // line searches of earlier phases of the last minimize call
+  // profiling: HIP events around each stage of every launched line search
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  double stage_ms[NSTAGE] = {0};
+  int prof_iters = 0;
   double eta_last = 0.0;
   int iters = 0, trace_n = 0;
   double last_rel = 0.0;
@@ -213,6 +227,7 @@ int ensure_inputs(omm_ctx* c) {
 }
 
 void invalidate(omm_ctx* c) {
+  c->phase_active = false;
   c->hs_valid = false;
   c->hs32_valid = false;
   c->s32_valid = false;
@@ -277,7 +292,7 @@ int prepare_precon(omm_ctx* c, double tau) {
   return OMM_OK;
 }
 
-int alloc_common(omm_ctx* c, int max_iter) {
+int alloc_common(omm_ctx* c) {
   const size_t mm = (size_t)c->M * c->M;
   TRY(dalloc(c, &c->HW, mm));
   TRY(dalloc(c, &c->SW, mm));
@@ -292,12 +307,6 @@ int alloc_common(omm_ctx* c, int max_iter) {
       c->st_host = nullptr;
       return fail(c, OMM_E_ALLOC, "hipHostMalloc failed");
     }
-  }
-  const int need = 2 * (max_iter + 2);
-  if (c->trace_cap < need) {
-    dfree(c->trace);
-    TRY(dalloc(c, &c->trace, (size_t)need));
-    c->trace_cap = need;
   }
   return OMM_OK;
 }
@@ -320,6 +329,35 @@ int initial_products(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* 
   return OMM_OK;
 }
 
+// Event marks for profiling: 8 per line search (before stage 0 and after each stage).
+int prof_mark(omm_ctx* c) {
+  if (!c->prof) return OMM_OK;
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used++], c->stream));
+  return OMM_OK;
+}
+
+// Fold recorded marks into per-stage milliseconds (synchronizes the stream).
+int prof_collect(omm_ctx* c) {
+  if (!c->prof || c->ev_used == 0) return OMM_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const size_t per = NSTAGE + 1;
+  for (size_t b = 0; b + per <= c->ev_used; b += per) {
+    for (int st = 0; st < NSTAGE; ++st) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[b + st], c->ev_pool[b + st + 1]));
+      c->stage_ms[st] += ms;
+    }
+    c->prof_iters += 1;
+  }
+  c->ev_used = 0;
+  return OMM_OK;
+}
+
 // One line search (the stage sequence in the header comment of this file).
 template <typename T>
 int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S,
@@ -330,6 +368,7 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   const int* done = &c->st->done;
   T* G = (k & 1) ? w.Gp : w.G;
   T* Gprev = (k & 1) ? w.G : w.Gp;
+  TRY(prof_mark(c));
   // G = 8 HC - 4 HW SC - 4 SW HC
   {
     GemmDesc d{compute, T_F64, et, et, et, KC, RC, 0, 1};
@@ -340,6 +379,7 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     op.K[1] = M;
     TRY(gemm(c, d, &op, 1, done));
   }
+  TRY(prof_mark(c));
   T* PG = G;
   if (P) {
     GemmDesc d{compute, et, et, et, et, KC, RC, 0, 1};
@@ -347,14 +387,17 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     TRY(gemm(c, d, &op, 1, done));
     PG = w.PG;
   }
+  TRY(prof_mark(c));
   HIPCHK(c, beta_and_direction<T>(G, PG, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials, c->st,
                                   c->stream));
+  TRY(prof_mark(c));
   {
     GemmDesc d{compute, et, et, et, et, KC, RC, 0, 1};
     GemmOp ops[2] = {make_op(M, N, N, w.D, N, Hs, N, w.HD, N),
                      make_op(M, N, N, w.D, N, S, N, w.SD, N)};
     TRY(gemm(c, d, ops, 2, done));
   }
+  TRY(prof_mark(c));
   {
     GemmDesc d{compute, et, et, T_F64, T_F64, KC, KC, 0, 1};
     GemmOp ops[4] = {make_op(M, M, N, w.D, N, w.HC, N, c->H1, M),
@@ -363,11 +406,14 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
                      make_op(M, M, N, w.D, N, w.SD, N, c->S2, M)};
     TRY(gemm(c, d, ops, 4, done));
   }
+  TRY(prof_mark(c));
   HIPCHK(c, line_search(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
                         c->stream));
+  TRY(prof_mark(c));
   HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, w.SD, mn, c->st, c->stream));
   HIPCHK(c, update_subspace(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
                             trace, c->stream));
+  TRY(prof_mark(c));
   return OMM_OK;
 }
 
@@ -377,34 +423,70 @@ int read_state(omm_ctx* c) {
   return OMM_OK;
 }
 
-// Runs one CG phase to tol / max_iter. Returns the device `done` code through *done_out.
+int ensure_trace(omm_ctx* c, int need) {
+  if (c->trace_cap >= need) return OMM_OK;
+  double* t = nullptr;
+  TRY(dalloc(c, &t, (size_t)need));
+  if (c->trace) {
+    HIPCHK(c, hipMemcpyAsync(t, c->trace, c->trace_cap * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c->trace);
+  }
+  c->trace = t;
+  c->trace_cap = need;
+  return OMM_OK;
+}
+
+// Starts a CG phase in precision T: initial products and E_0 (the state's iteration count 0).
 template <typename T>
-int run_phase(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, const T* P, double tol,
-              int max_iter, int trace_off, int* iters_out, int* done_out) {
+int phase_begin(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, double tol,
+                int trace_off) {
   DevState init{};
   init.tol = tol;
-  init.max_iter = max_iter;
-  init.done = 0;
-  init.iter = 0;
+  init.max_iter = 0;
   HIPCHK(c, hipMemcpyAsync(c->st, &init, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
-  double* trace = c->trace + trace_off;
-  TRY(initial_products<T>(c, w, compute, Hs, S, trace));
+  TRY(ensure_trace(c, trace_off + 2));
+  TRY(initial_products<T>(c, w, compute, Hs, S, c->trace + trace_off));
   TRY(read_state(c));
-  if (c->st_host->done == 0 && max_iter <= 0) {
-    *iters_out = 0;
-    *done_out = 2;
+  c->phase_active = true;
+  c->phase_k = 0;
+  c->trace_off = trace_off;
+  return OMM_OK;
+}
+
+// Up to `count` more line searches of the active phase (stops early on convergence / error).
+template <typename T>
+int phase_iterate(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, const T* P,
+                  double tol, int count, int* done_out) {
+  DevState* h = c->st_host;
+  if (h->done < 0) {
+    *done_out = h->done;
     return OMM_OK;
   }
+  h->done = 0;
+  h->tol = tol;
+  h->max_iter = h->iter + count;
+  TRY(ensure_trace(c, c->trace_off + h->max_iter + 2));
+  HIPCHK(c, hipMemcpyAsync(c->st, h, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  double* trace = c->trace + c->trace_off;
   // Host checks the device state every `check` launches; iterations launched after the stop
   // return immediately.
   const int check = c->N >= 4096 ? 2 : 8;
-  for (int k = 0; k < max_iter && c->st_host->done == 0; ++k) {
-    TRY(line_search_iteration<T>(c, w, compute, Hs, S, P, k, trace));
-    if ((k + 1) % check == 0 || k + 1 == max_iter) TRY(read_state(c));
+  if (count > 0) {
+    for (int k = 0; k < count; ++k) {
+      TRY(line_search_iteration<T>(c, w, compute, Hs, S, P, c->phase_k, trace));
+      c->phase_k += 1;
+      if ((k + 1) % check == 0 || k + 1 == count) {
+        TRY(read_state(c));
+        if (h->done != 0) break;
+      }
+    }
+    TRY(prof_collect(c));
   }
   TRY(read_state(c));
-  *iters_out = c->st_host->iter;
-  *done_out = c->st_host->done;
+  *done_out = count > 0 ? h->done : 2;
+  if (*done_out == 0) *done_out = 2;
   return OMM_OK;
 }
 
@@ -430,7 +512,7 @@ int minimize_impl(omm_ctx* c, const double* C0, bool C0_device, double eta, doub
     return fail(c, OMM_E_ARG, "need tol >= 0, max_iter >= 0, finite eta, non-NaN tau");
   if (!C0 && !c->have_C) return fail(c, OMM_E_STATE, "no C0 given and no C to resume from");
   const size_t mn = (size_t)c->M * c->N;
-  TRY(alloc_common(c, max_iter));
+  TRY(alloc_common(c));
   TRY(alloc_work<double>(c, c->w64));
   if (c->mode != OMM_FP64) TRY(alloc_work<float>(c, c->w32));
   TRY(prepare_shift(c, eta));
@@ -449,31 +531,39 @@ int minimize_impl(omm_ctx* c, const double* C0, bool C0_device, double eta, doub
     HIPCHK(c, convert_f32_f64(c->w32.C, c->w64.C, (int64_t)mn, c->stream));
   c->have_C = true;
 
-  int iters1 = 0, done1 = 0, iters2 = 0, done2 = 0;
+  int done1 = 0, done2 = 0;
   c->iters = 0;
+  c->iters_before = 0;
   if (c->mode == OMM_FP64) {
-    TRY(run_phase<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr, tol,
-                          max_iter, 0, &iters1, &done1));
+    TRY(phase_begin<double>(c, c->w64, CF64, c->Hs, c->S, tol, 0));
+    c->phase_prec = OMM_FP64;
+    TRY(phase_iterate<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr, tol,
+                              max_iter, &done1));
     c->c_prec = OMM_FP64;
-    c->iters = iters1;
-    c->trace_n = iters1 + 1;
-    c->last_rel = 0.0;
+    c->iters = c->st_host->iter;
+    c->trace_n = c->iters + 1;
   } else {
     const int comp = compute_of(c->mode);
     const double tol1 = c->refine ? fmax(tol, c->mixed_tol) : tol;
-    TRY(run_phase<float>(c, c->w32, comp, c->Hs32, c->S32, c->p_kind > 0 ? c->P32 : nullptr, tol1,
-                         max_iter, 0, &iters1, &done1));
+    TRY(phase_begin<float>(c, c->w32, comp, c->Hs32, c->S32, tol1, 0));
+    c->phase_prec = c->mode;
+    TRY(phase_iterate<float>(c, c->w32, comp, c->Hs32, c->S32, c->p_kind > 0 ? c->P32 : nullptr,
+                             tol1, max_iter, &done1));
     c->c_prec = c->mode;
+    const int iters1 = c->st_host->iter;
     c->iters = iters1;
     c->trace_n = iters1 + 1;
     if (done1 < 0) return status_of_done(c, done1);
     if (c->refine) {
       HIPCHK(c, convert_f32_f64(c->w32.C, c->w64.C, (int64_t)mn, c->stream));
-      TRY(run_phase<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr, tol,
-                            max_iter, iters1 + 1, &iters2, &done2));
       c->c_prec = OMM_FP64;
-      c->iters = iters1 + iters2;
-      c->trace_n = iters1 + 1 + iters2 + 1;
+      c->iters_before = iters1;
+      TRY(phase_begin<double>(c, c->w64, CF64, c->Hs, c->S, tol, iters1 + 1));
+      c->phase_prec = OMM_FP64;
+      TRY(phase_iterate<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr,
+                                tol, max_iter, &done2));
+      c->iters = iters1 + c->st_host->iter;
+      c->trace_n = iters1 + 1 + c->st_host->iter + 1;
       done1 = done2;
     }
   }
@@ -554,6 +644,7 @@ int omm_destroy(omm_ctx* c) {
   dfree(c->partials); dfree(c->ws); dfree(c->st); dfree(c->flags); dfree(c->trace);
   dfree(c->nn_scratch); dfree(c->inv_work);
   if (c->st_host) hipHostFree(c->st_host);
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own) hipStreamDestroy(c->own);
   delete c;
   return OMM_OK;
@@ -751,12 +842,62 @@ int omm_stats(omm_ctx* c, int* iters, double* last_rel) {
   return OMM_OK;
 }
 
+int omm_phase_stats(omm_ctx* c, int* mixed_iters, int* fp64_iters) {
+  if (!c) return OMM_E_ARG;
+  const int last = c->iters - c->iters_before;  // line searches of the active phase
+  if (mixed_iters) *mixed_iters = c->phase_prec != OMM_FP64 ? last : c->iters_before;
+  if (fp64_iters) *fp64_iters = c->phase_prec == OMM_FP64 ? last : 0;
+  return OMM_OK;
+}
+
 int omm_energy_trace(omm_ctx* c, double* buf, int cap, int* n) {
   if (!c || (!buf && cap > 0)) return c ? fail(c, OMM_E_ARG, "null buffer") : OMM_E_ARG;
   const int k = (int)c->trace_host.size() < cap ? (int)c->trace_host.size() : cap;
   for (int i = 0; i < k; ++i) buf[i] = c->trace_host[i];
   if (n) *n = (int)c->trace_host.size();
   return OMM_OK;
+}
+
+int omm_iterate(omm_ctx* c, int count, double tol) {
+  if (!c) return OMM_E_ARG;
+  if (count < 0 || !(tol >= 0.0)) return fail(c, OMM_E_ARG, "need count >= 0 and tol >= 0");
+  if (!c->phase_active) return fail(c, OMM_E_STATE, "no active minimization to continue");
+  int done = 0;
+  if (c->phase_prec == OMM_FP64) {
+    TRY(phase_iterate<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr, tol,
+                              count, &done));
+    c->c_prec = OMM_FP64;
+  } else {
+    TRY(phase_iterate<float>(c, c->w32, compute_of(c->phase_prec), c->Hs32, c->S32,
+                             c->p_kind > 0 ? c->P32 : nullptr, tol, count, &done));
+    c->c_prec = c->phase_prec;
+  }
+  c->iters = c->iters_before + c->st_host->iter;
+  c->trace_n = c->trace_off + c->st_host->iter + 1;
+  c->last_rel = c->st_host->rel_change;
+  c->trace_host.assign((size_t)c->trace_n, 0.0);
+  HIPCHK(c, hipMemcpyAsync(c->trace_host.data(), c->trace, c->trace_n * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return status_of_done(c, done);
+}
+
+int omm_set_profiling(omm_ctx* c, int on) {
+  if (!c) return OMM_E_ARG;
+  TRY(prof_collect(c));
+  c->prof = on != 0;
+  c->ev_used = 0;
+  for (int i = 0; i < NSTAGE; ++i) c->stage_ms[i] = 0.0;
+  c->prof_iters = 0;
+  return OMM_OK;
+}
+
+int omm_stage_times(omm_ctx* c, double* ms, int cap, int* iters) {
+  if (!c || (!ms && cap > 0)) return c ? fail(c, OMM_E_ARG, "null buffer") : OMM_E_ARG;
+  TRY(prof_collect(c));
+  for (int i = 0; i < cap && i < NSTAGE; ++i) ms[i] = c->stage_ms[i];
+  if (iters) *iters = c->prof_iters;
+  return NSTAGE;
 }
 
 const char* omm_last_error(const omm_ctx* c) {

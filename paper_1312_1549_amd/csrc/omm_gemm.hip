@@ -182,7 +182,8 @@ __global__ __launch_bounds__(256) void gemm_k4(GemmBatch batch, const int* done,
     }
   }
 
-  // Epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 block.
+  // Epilogue: lane holds column lane%16 of each 16x16 block; its 4 accumulator values are rows
+  // 4*(lane/16)+r for the FP32 instruction and rows lane/16+4r for the FP64 one.
   const int nops = gridDim.z;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -190,7 +191,8 @@ __global__ __launch_bounds__(256) void gemm_k4(GemmBatch batch, const int* done,
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * TM * 16 + i * 16 + 4 * (lane >> 4) + r;
+        const int rr = sizeof(CT) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        const int row = m0 + wm * TM * 16 + i * 16 + rr;
         const int col = n0 + wn * TN * 16 + j * 16 + (lane & 15);
         if (row < op.M && col < op.N) {
           const double s = (double)acc[i][j][r];

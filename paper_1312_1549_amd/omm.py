@@ -125,6 +125,24 @@ class OMM:
         return self._check(self._L.omm_minimize(self._h, ptr, float(eta), float(tau), float(tol),
                                                 int(max_iter)))
 
+    def iterate(self, count: int, tol: float = 0.0) -> int:
+        """Continue the last minimization for up to `count` line searches (no setup)."""
+        self._bind_stream()
+        return self._check(self._L.omm_iterate(self._h, int(count), float(tol)))
+
+    STAGES = ("gradient", "precondition", "direction", "operator_products", "projections",
+              "line_search", "update")
+
+    def set_profiling(self, on: bool = True):
+        self._check(self._L.omm_set_profiling(self._h, 1 if on else 0))
+
+    def stage_times(self):
+        """(dict stage -> accumulated ms, profiled line searches)."""
+        buf = (ct.c_double * 7)()
+        it = ct.c_int()
+        self._check(self._L.omm_stage_times(self._h, buf, 7, ct.byref(it)))
+        return dict(zip(self.STAGES, list(buf))), it.value
+
     def energy(self) -> float:
         e = ct.c_double()
         self._check(self._L.omm_energy(self._h, ct.byref(e)))
@@ -174,6 +192,12 @@ class OMM:
         rel = ct.c_double()
         self._check(self._L.omm_stats(self._h, ct.byref(it), ct.byref(rel)))
         return it.value, rel.value
+
+    def phase_stats(self):
+        """(mixed-precision line searches, FP64 line searches) of the last minimize call."""
+        a, b = ct.c_int(), ct.c_int()
+        self._check(self._L.omm_phase_stats(self._h, ct.byref(a), ct.byref(b)))
+        return a.value, b.value
 
     def energy_trace(self) -> np.ndarray:
         n = ct.c_int()

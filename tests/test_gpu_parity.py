@@ -1,0 +1,223 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle and with closed forms.
+
+Every case prints its name, shape and seed before touching the GPU.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import brute, omm as oracle
+from synth import config_system, make_system, lattice_positions, start_coefficients
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib_ok():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1312_1549_amd import OMM
+
+    return OMM
+
+
+@pytest.fixture(scope="module")
+def c1():
+    s = config_system("c1", 0)
+    return s, start_coefficients(s.S, s.M, 1), brute.generalized_eigh_lapack(s.H, s.S)[0]
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # 50 atoms (5x5x2 lattice) x 4 orbitals -> N = 200, M = 37: ragged against 64/128 tiles
+    rng = np.random.default_rng(21)
+    pos = lattice_positions((5, 5, 2), 2.5)
+    pos = pos + rng.uniform(-0.2, 0.2, size=pos.shape)
+    s = make_system(pos, 4, 6.0, 37, rng, name="ragged", eta=0.5, tau=10.0, seed=21)
+    return s, start_coefficients(s.S, s.M, 22), brute.generalized_eigh_lapack(s.H, s.S)[0]
+
+
+@pytest.fixture(scope="module")
+def c2():
+    s = config_system("c2", 0)
+    return s, start_coefficients(s.S, s.M, 1), brute.generalized_eigh_lapack(s.H, s.S, s.M + 1)[0]
+
+
+def _run(OMM, s, C0, eta, tau, tol, max_iter, precision="fp64", refine=True):
+    solver = OMM(s.N, s.M, precision=precision, refine=refine)
+    solver.set_HS(s.H, s.S, s.T)
+    status = solver.minimize(C0, eta=eta, tau=tau, tol=tol, max_iter=max_iter)
+    return solver, status
+
+
+@pytest.mark.parametrize("tau", [10.0, math.inf, 0.0])
+def test_fp64_c1_matches_oracle_and_closed_form(lib_ok, c1, tau):
+    s, C0, w = c1
+    eta = 0.5
+    _say(f"fp64 c1 N={s.N} M={s.M} eta={eta} tau={tau} seed=0/1")
+    solver, status = _run(lib_ok, s, C0, eta, tau, 1e-14, 5000)
+    assert status == 0
+    E = solver.energy()
+    E_ref = brute.closed_form_energy(w, s.M, eta)
+    assert abs(E - E_ref) <= 1e-10 * abs(E_ref)
+    ref = oracle.minimize(s.H, s.S, s.T, C0, eta, tau, 1e-14, 5000)
+    tr = solver.energy_trace()
+    n = min(30, len(tr), len(ref.energies))
+    np.testing.assert_allclose(tr[:n], ref.energies[:n], rtol=1e-10, atol=0)
+    it, _ = solver.stats()
+    assert abs(it - ref.iterations) <= max(5, 0.1 * ref.iterations)
+    HW, SW = solver.subspace()
+    assert np.max(np.abs(SW - np.eye(s.M))) < 1e-4
+    # outputs: density and energy-density matrices of the GPU's own C, element by element
+    C = solver.get_C()
+    SW_c = C @ s.S @ C.T
+    HW_c = C @ (s.H - eta * s.S) @ C.T
+    np.testing.assert_allclose(SW, SW_c, rtol=0, atol=1e-11 * np.max(np.abs(SW_c)))
+    np.testing.assert_allclose(HW, HW_c, rtol=0, atol=1e-11 * np.max(np.abs(HW_c)))
+    rho = solver.density()
+    edm = solver.edm()
+    np.testing.assert_allclose(rho, oracle.density(C, SW_c), rtol=0, atol=1e-12 * np.abs(rho).max())
+    np.testing.assert_allclose(edm, oracle.energy_density(C, HW_c), rtol=0,
+                               atol=1e-12 * np.abs(edm).max())
+    # density of the minimum is unique (gap > 0): compare with the eigenvector projector
+    gH, _ = brute.eigen_gradients(s.H, s.S, s.M)
+    assert np.linalg.norm(rho - gH) < 1e-5 * np.linalg.norm(gH)
+
+
+def test_fp64_eta_below_occupied_level(lib_ok, c1):
+    s, C0, w = c1
+    _say(f"fp64 c1 eta=0 regime N={s.N} M={s.M}")
+    solver, status = _run(lib_ok, s, C0, 0.0, 10.0, 1e-14, 5000)
+    E_ref = brute.closed_form_energy(w, s.M, 0.0)
+    assert abs(solver.energy() - E_ref) <= 1e-9 * abs(E_ref)
+    _, SW = solver.subspace()
+    ev = np.linalg.eigvalsh(SW)
+    assert np.sum(ev > 0.5) == int(np.sum(w[: s.M] < 0.0))
+
+
+def test_fp64_ragged_shapes(lib_ok, ragged):
+    s, C0, w = ragged
+    _say(f"fp64 ragged N={s.N} M={s.M} seed=21/22")
+    solver, status = _run(lib_ok, s, C0, 0.5, 10.0, 1e-14, 5000)
+    E_ref = brute.closed_form_energy(w, s.M, 0.5)
+    assert abs(solver.energy() - E_ref) <= 1e-10 * abs(E_ref)
+    ref = oracle.minimize(s.H, s.S, s.T, C0, 0.5, 10.0, 1e-14, 40)
+    tr = solver.energy_trace()
+    np.testing.assert_allclose(tr[:30], ref.energies[:30], rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("tau", [10.0, math.inf])
+def test_preconditioner_matches_inverse(lib_ok, ragged, c1, tau):
+    for s, C0, _ in (c1, ragged):
+        _say(f"precon N={s.N} tau={tau}")
+        solver, _ = _run(lib_ok, s, C0, 0.5, tau, 1e-8, 2)
+        P = solver.preconditioner()
+        ref = oracle.preconditioner(s.S, s.T, tau)
+        np.testing.assert_allclose(P, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def test_fp64_c2_trajectory_and_minimum(lib_ok, c2):
+    s, C0, w = c2
+    eta, tau = 0.5, 10.0
+    _say(f"fp64 c2 N={s.N} M={s.M} eta={eta} tau={tau}")
+    solver, status = _run(lib_ok, s, C0, eta, tau, 1e-14, 3000)
+    E_ref = brute.closed_form_energy(w, s.M, eta)
+    assert abs(solver.energy() - E_ref) <= 1e-10 * abs(E_ref)
+    ref = oracle.minimize(s.H, s.S, s.T, C0, eta, tau, 0.0, 25)
+    tr = solver.energy_trace()
+    np.testing.assert_allclose(tr[:26], ref.energies[:26], rtol=1e-10, atol=0)
+    P = solver.preconditioner()
+    k = np.random.default_rng(0).integers(0, s.N, size=(64, 2))
+    Pref = np.linalg.inv(s.S + s.T / tau)
+    np.testing.assert_allclose(P[k[:, 0], k[:, 1]], Pref[k[:, 0], k[:, 1]], rtol=0,
+                               atol=1e-11 * np.abs(Pref).max())
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mixed_precision_c2(lib_ok, c2, precision):
+    s, C0, w = c2
+    eta, tau = 0.5, 10.0
+    E_ref = brute.closed_form_energy(w, s.M, eta)
+    _say(f"{precision} c2 no refinement")
+    solver, status = _run(lib_ok, s, C0, eta, tau, 1e-9, 3000, precision=precision, refine=False)
+    err_mixed = abs(solver.energy() - E_ref) / abs(E_ref)
+    print(f"{precision}: mixed-only rel err {err_mixed:.3e} iters {solver.stats()[0]}")
+    assert err_mixed < 1e-5
+    _say(f"{precision} c2 with FP64 refinement")
+    solver, status = _run(lib_ok, s, C0, eta, tau, 1e-13, 3000, precision=precision, refine=True)
+    err = abs(solver.energy() - E_ref) / abs(E_ref)
+    print(f"{precision}+refine: rel err {err:.3e} iters {solver.stats()[0]}")
+    assert err < 1e-8
+
+
+def test_error_paths(lib_ok, c1):
+    from paper_1312_1549_amd import OMMError
+
+    s, C0, _ = c1
+    _say("error paths")
+    solver = lib_ok(s.N, s.M)
+    with pytest.raises(OMMError) as e:
+        solver.minimize(C0, eta=0.5, tau=10.0)
+    assert e.value.code == -2  # no H/S yet
+    H = s.H.copy()
+    H[0, 1] += 1e-3
+    with pytest.raises(OMMError) as e:
+        solver.set_HS(H, s.S, s.T)
+    assert e.value.code == -9
+    H = s.H.copy()
+    H[3, 3] = np.nan
+    with pytest.raises(OMMError) as e:
+        solver.set_HS(H, s.S, s.T)
+    assert e.value.code == -5
+    solver.set_HS(s.H, s.S, None)
+    with pytest.raises(OMMError) as e:
+        solver.minimize(C0, eta=0.5, tau=10.0)  # finite tau needs T
+    assert e.value.code == -1
+    with pytest.raises(OMMError) as e:
+        solver.minimize(None, eta=0.5, tau=0.0)  # nothing to resume from
+    assert e.value.code == -2
+    with pytest.raises(OMMError) as e:
+        solver.iterate(3)
+    assert e.value.code == -2
+    # a start far outside the basin: the line search runs out of minima or diverges
+    solver.set_HS(s.H, s.S, s.T)
+    big = 30.0 * C0 / np.linalg.norm(C0) * math.sqrt(s.M)
+    with pytest.raises(OMMError) as e:
+        solver.minimize(big, eta=0.0, tau=0.0, tol=1e-14, max_iter=500)
+    assert e.value.code in (-7, -8)
+
+
+def test_resume_and_iterate(lib_ok, c1):
+    s, C0, w = c1
+    _say("resume / iterate")
+    solver, _ = _run(lib_ok, s, C0, 0.5, 10.0, 0.0, 10)
+    e10 = solver.energy_trace()
+    st = solver.iterate(10)
+    assert st == 1
+    e20 = solver.energy_trace()
+    ref = oracle.minimize(s.H, s.S, s.T, C0, 0.5, 10.0, 0.0, 20)
+    np.testing.assert_allclose(e20[:21], ref.energies[:21], rtol=1e-10, atol=0)
+    assert np.array_equal(e10[:11], e20[:11])
+    # warm start from the converged C reaches the minimum in a few line searches
+    solver.minimize(C0, eta=0.5, tau=10.0, tol=1e-14, max_iter=5000)
+    solver.minimize(None, eta=0.5, tau=10.0, tol=1e-12, max_iter=5000)
+    assert solver.stats()[0] <= 5
+
+
+def test_profiling_counts_stages(lib_ok, c1):
+    s, C0, _ = c1
+    _say("profiling")
+    solver, _ = _run(lib_ok, s, C0, 0.5, 10.0, 0.0, 2)
+    solver.set_profiling(True)
+    solver.iterate(6)
+    t, n = solver.stage_times()
+    assert n == 6 and all(v >= 0 for v in t.values()) and t["operator_products"] > 0
