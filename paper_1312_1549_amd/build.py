@@ -19,8 +19,9 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 BUILD = ROOT / "_build"
 LIB = PKG / "libomm.so"
-SOURCES = ["omm_gemm.hip", "omm_kernels.hip", "omm_precon.hip", "omm_context.hip", "omm_batch.hip"]
-HEADERS = [CSRC / "omm_internal.h", ROOT / "include" / "omm.h"]
+SOURCES = ["omm_gemm_bf16x3.hip", "omm_gemm_f32.hip", "omm_gemm_f64.hip", "omm_gemm.hip",
+           "omm_kernels.hip", "omm_precon.hip", "omm_context.hip", "omm_batch.hip"]
+HEADERS = [CSRC / "omm_internal.h", CSRC / "omm_gemm_impl.h", ROOT / "include" / "omm.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("OMM_OFFLOAD_ARCH", "gfx950")

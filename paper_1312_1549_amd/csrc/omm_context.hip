@@ -14,8 +14,11 @@
 // to learn whether the run has stopped (later iterations are launched but return at once).
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -152,8 +155,10 @@ void free_work(Work<T>& w) {
   dfree(w.HD); dfree(w.SD);
 }
 
-// Tile / split-K choice for one GEMM shape (M x N output, K inner).
-void choose_tiling(GemmDesc& d, int M, int N, int K) {
+// ---- tile / split-K choice --------------------------------------------------------------------
+// Heuristic: the largest macro tile that still yields >= 1 workgroup per CU, split-K when even
+// the 64x64 tiling leaves CUs idle and K is long. The autotuner replaces it per shape.
+void heuristic_tiling(GemmDesc& d, int M, int N, int K) {
   const int cus = 256;
   const long t128 = (long)((M + 127) / 128) * ((N + 127) / 128);
   const long t64 = (long)((M + 63) / 64) * ((N + 63) / 64);
@@ -169,18 +174,137 @@ void choose_tiling(GemmDesc& d, int M, int N, int K) {
   }
 }
 
-int gemm(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, const int* done) {
-  const int K = ops[0].K[0] + (ops[0].nseg > 1 ? ops[0].K[1] : 0);
-  choose_tiling(d, ops[0].M, ops[0].N, K);
-  if (d.splitk > 1) {
-    const size_t need = gemm_splitk_ws_bytes(ops, nops, d.splitk);
-    if (need > c->ws_bytes) {
-      dfree(c->ws);
-      c->ws_bytes = 0;
-      TRY(dalloc(c, &c->ws, need / sizeof(double) + 1));
-      c->ws_bytes = need;
+struct TuneKey {
+  int v[11];
+  bool operator<(const TuneKey& o) const {
+    for (int i = 0; i < 11; ++i)
+      if (v[i] != o.v[i]) return v[i] < o.v[i];
+    return false;
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;  // -> (tile, splitk)
+bool g_tune_loaded = false;
+
+const char* tune_cache_path() { return getenv("OMM_AUTOTUNE_CACHE"); }
+
+bool autotune_enabled() {
+  const char* e = getenv("OMM_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  TuneKey k;
+  int t, sk;
+  while (fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d", &k.v[0], &k.v[1], &k.v[2], &k.v[3],
+                &k.v[4], &k.v[5], &k.v[6], &k.v[7], &k.v[8], &k.v[9], &k.v[10], &t, &sk) == 13)
+    g_tune[k] = {t, sk};
+  fclose(f);
+}
+
+void tune_save_locked() {
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  for (const auto& kv : g_tune) {
+    for (int i = 0; i < 11; ++i) fprintf(f, "%d ", kv.first.v[i]);
+    fprintf(f, "%d %d\n", kv.second.first, kv.second.second);
+  }
+  fclose(f);
+}
+
+int ensure_ws(omm_ctx* c, const GemmOp* ops, int nops, int splitk) {
+  if (splitk <= 1) return OMM_OK;
+  const size_t need = gemm_splitk_ws_bytes(ops, nops, splitk);
+  if (need > c->ws_bytes) {
+    dfree(c->ws);
+    c->ws_bytes = 0;
+    TRY(dalloc(c, &c->ws, need / sizeof(double) + 1));
+    c->ws_bytes = need;
+  }
+  return OMM_OK;
+}
+
+// Times each candidate (tile, split-K) once after a warm-up launch; returns the fastest.
+int autotune(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, int K, std::pair<int, int>* best) {
+  const int M = ops[0].M, N = ops[0].N;
+  std::vector<std::pair<int, int>> cands;
+  for (int t = 0; t < gemm_num_tiles(); ++t) {
+    GemmDesc dt = d;
+    dt.tile = t;
+    dt.splitk = 1;
+    if (!gemm_supported(dt)) continue;
+    const int bm = t == 1 ? 64 : (t == 2 ? 256 : 128), bn = t == 1 ? 64 : (t == 3 ? 256 : 128);
+    const long tiles = (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+    if (tiles >= 32 || t == 1) cands.push_back({t, 1});
+    for (int sk : {2, 4, 8, 16})
+      if (tiles * sk <= 4096 && tiles < 512 && K / sk >= 256) cands.push_back({t, sk});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  *best = {-1, 1};
+  for (const auto& cand : cands) {
+    GemmDesc dt = d;
+    dt.tile = cand.first;
+    dt.splitk = cand.second;
+    TRY(ensure_ws(c, ops, nops, dt.splitk));
+    HIPCHK(c, gemm_launch(dt, ops, nops, nullptr, c->ws, c->ws_bytes, c->stream));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    HIPCHK(c, gemm_launch(dt, ops, nops, nullptr, c->ws, c->ws_bytes, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      *best = cand;
     }
   }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return OMM_OK;
+}
+
+// One GEMM launch with a tuned (or heuristic) tiling. `tunable` is false for in-place updates,
+// which must not be run more than once.
+int gemm(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, const int* done, bool tunable = true) {
+  const int K = ops[0].K[0] + (ops[0].nseg > 1 ? ops[0].K[1] : 0);
+  const int M = ops[0].M, N = ops[0].N;
+  heuristic_tiling(d, M, N, K);
+  const double flops = 2.0 * M * N * (double)K * nops;
+  if (tunable && flops >= 2e9 && autotune_enabled()) {
+    TuneKey key{{d.compute, d.ta, d.tb, d.tc, d.tx, d.la, d.lb, M, N, K, nops}};
+    std::pair<int, int> choice{-1, 1};
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      tune_load_locked();
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) choice = it->second;
+    }
+    if (choice.first < 0) {
+      TRY(autotune(c, d, ops, nops, K, &choice));
+      if (choice.first >= 0) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[key] = choice;
+        tune_save_locked();
+      }
+    }
+    if (choice.first >= 0) {
+      d.tile = choice.first;
+      d.splitk = choice.second;
+    }
+  }
+  TRY(ensure_ws(c, ops, nops, d.splitk));
   HIPCHK(c, gemm_launch(d, ops, nops, done, c->ws, c->ws_bytes, c->stream));
   return OMM_OK;
 }

@@ -1,0 +1,402 @@
+// MFMA GEMM tile loop for gfx950 (included by the per-precision translation units).
+//
+//   C = alpha * sum_seg A_seg * B_seg + beta * X       (up to 2 summed K segments)
+//
+// Operand tiles are staged in LDS as [row][k] (k contiguous), double-buffered: while the waves
+// run the MFMAs of tile t from one buffer, the global loads of tile t+1 are in flight and are
+// written to the other buffer afterwards, so each K tile costs one barrier. k-contiguous
+// operands are read with 16-byte (or wider) vector loads; the symmetric operators Hs, S and P are
+// always read that way (P^T = P). Row strides are padded so that MFMA fragment reads hit
+// distinct LDS banks.
+//
+// Modes:
+//   CF64     v_mfma_f64_16x16x4f64   A, B fragments: lane l holds (row l%16, k l/16);
+//                                     result rows l/16 + 4r, column l%16.
+//   CF32     v_mfma_f32_16x16x4f32   same fragments; result rows 4(l/16) + r.
+//   CBF16X3  v_mfma_f32_16x16x32_bf16 on a hi/lo split of each operand (a = hi + lo,
+//            hi = bf16(a), lo = bf16(a - hi)); three products lo*hi + hi*lo + hi*hi per K step,
+//            FP32 accumulation. Lane l holds row l%16, k 8(l/16)..8(l/16)+7; result rows
+//            4(l/16) + r. The split happens while a tile is staged, so operands stay FP32/FP64
+//            in HBM.
+#pragma once
+
+#include "omm_internal.h"
+
+namespace omm {
+namespace gemm_detail {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct GemmBatch {
+  GemmOp op[4];
+};
+
+typedef void (*gemm_fn)(GemmBatch, const int*, int, double*);
+
+__device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T ldg(const void* p, int64_t i) {
+  return static_cast<const T*>(p)[i];
+}
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+
+// Linear workgroup id -> (tm, tn): each of the 8 XCDs gets a contiguous run of tiles, M fastest,
+// so tiles sharing a column panel of B are co-resident on one XCD (shared L2).
+__device__ __forceinline__ bool tile_of(int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int total = tiles_m * tiles_n;
+  const int per = (total + 7) >> 3;
+  const int bid = blockIdx.x;
+  const int t = (bid & 7) * per + (bid >> 3);
+  if (t >= total) return false;
+  tm = t % tiles_m;
+  tn = t / tiles_m;
+  return true;
+}
+
+// K range [kb, ke) of segment `seg` owned by split `sp` (splits cut the concatenated K of all
+// segments into BK-aligned chunks).
+template <int BK>
+__device__ __forceinline__ void split_range(const GemmOp& op, int seg, int sp, int nsplit, int& kb,
+                                            int& ke) {
+  const int ktot = op.K[0] + (op.nseg > 1 ? op.K[1] : 0);
+  const int nk = (ktot + BK - 1) / BK;
+  const int per = (nk + nsplit - 1) / nsplit;
+  const int g0 = sp * per * BK, g1 = min(ktot, (sp + 1) * per * BK);
+  const int off = seg == 0 ? 0 : op.K[0];
+  kb = max(g0 - off, 0);
+  ke = min(g1 - off, op.K[seg]);
+}
+
+// Per-mode element types: LDS element, register staging element, vector width of KC loads.
+template <int MODE>
+struct ModeTraits;
+template <>
+struct ModeTraits<CF64> {
+  typedef double lds_t;
+  static constexpr int VEC = 2;  // 16 B
+  static constexpr int PAD = 2;
+};
+template <>
+struct ModeTraits<CF32> {
+  typedef float lds_t;
+  static constexpr int VEC = 4;  // 16 B
+  static constexpr int PAD = 4;
+};
+template <>
+struct ModeTraits<CBF16X3> {
+  typedef unsigned short lds_t;
+  static constexpr int VEC = 8;  // 8 elements -> one 16-byte hi and one 16-byte lo LDS write
+  static constexpr int PAD = 8;
+};
+
+// Global -> register staging of one operand tile (R rows x BK), `NV` vectors of VEC per thread.
+// KC: vector = VEC consecutive k of one row. RC: vector = VEC consecutive rows of one k.
+template <int MODE, typename TS, int LAYOUT, int R, int BK, int NT>
+struct Stager {
+  static constexpr int VEC = ModeTraits<MODE>::VEC;
+  static constexpr int NV = R * BK / VEC / NT;
+  static_assert(R * BK % (VEC * NT) == 0, "tile not divisible among threads");
+  typedef typename ModeTraits<MODE>::lds_t lds_t;
+  static constexpr int RS = BK + ModeTraits<MODE>::PAD;  // LDS row stride (elements)
+  float rf[MODE == CF64 ? 1 : NV * VEC];
+  double rd[MODE == CF64 ? NV * VEC : 1];
+
+  __device__ __forceinline__ void coords(int tid, int v, int& r, int& k) const {
+    const int e = tid + v * NT;
+    if (LAYOUT == KC) {
+      r = e / (BK / VEC);
+      k = (e % (BK / VEC)) * VEC;
+    } else {
+      k = e / (R / VEC);
+      r = (e % (R / VEC)) * VEC;
+    }
+  }
+
+  __device__ __forceinline__ void put(int idx, double v) {
+    if constexpr (MODE == CF64) rd[idx] = v; else rf[idx] = (float)v;
+  }
+
+  __device__ __forceinline__ void load(const void* X, int64_t ld, int r0, int rmax, int k0, int ke,
+                                       int tid, bool vec_ok) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      int r, k;
+      coords(tid, v, r, k);
+      const int gr = r0 + r, gk = k0 + k;
+      if (LAYOUT == KC) {
+        const bool full = vec_ok && gr < rmax && gk + VEC <= ke;
+        const TS* p = static_cast<const TS*>(X) + (int64_t)gr * ld + gk;
+        if (full) {
+          if constexpr (sizeof(TS) == 8) {
+#pragma unroll
+            for (int u = 0; u < VEC; u += 2) {
+              const double2 q = *reinterpret_cast<const double2*>(p + u);
+              put(v * VEC + u, q.x);
+              put(v * VEC + u + 1, q.y);
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < VEC; u += 4) {
+              const float4 q = *reinterpret_cast<const float4*>(p + u);
+              put(v * VEC + u, q.x);
+              put(v * VEC + u + 1, q.y);
+              put(v * VEC + u + 2, q.z);
+              put(v * VEC + u + 3, q.w);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u)
+            put(v * VEC + u, (gr < rmax && gk + u < ke) ? (double)p[u] : 0.0);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) {
+          const bool in = gr + u < rmax && gk < ke;
+          put(v * VEC + u, in ? (double)ldg<TS>(X, (int64_t)gk * ld + gr + u) : 0.0);
+        }
+      }
+    }
+  }
+
+  // Registers -> LDS buffer(s) [R][RS]. BF16X3 writes hi to s0 and lo to s1.
+  __device__ __forceinline__ void store(lds_t* s0, lds_t* s1, int tid) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      int r, k;
+      coords(tid, v, r, k);
+      if constexpr (MODE == CBF16X3) {
+        if (LAYOUT == KC) {
+          u16x8 h, l;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const float x = rf[v * VEC + u];
+            const unsigned short hb = bf16_rne(x);
+            h[u] = hb;
+            l[u] = bf16_rne(x - bf16_val(hb));
+          }
+          *reinterpret_cast<u16x8*>(s0 + r * RS + k) = h;
+          *reinterpret_cast<u16x8*>(s1 + r * RS + k) = l;
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) {
+            const float x = rf[v * VEC + u];
+            const unsigned short hb = bf16_rne(x);
+            s0[(r + u) * RS + k] = hb;
+            s1[(r + u) * RS + k] = bf16_rne(x - bf16_val(hb));
+          }
+        }
+      } else if constexpr (MODE == CF64) {
+        if (LAYOUT == KC) {
+#pragma unroll
+          for (int u = 0; u < VEC; u += 2)
+            *reinterpret_cast<double2*>(s0 + r * RS + k + u) = double2{rd[v * VEC + u], rd[v * VEC + u + 1]};
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) s0[(r + u) * RS + k] = rd[v * VEC + u];
+        }
+      } else {
+        if (LAYOUT == KC) {
+#pragma unroll
+          for (int u = 0; u < VEC; u += 4)
+            *reinterpret_cast<float4*>(s0 + r * RS + k + u) =
+                float4{rf[v * VEC + u], rf[v * VEC + u + 1], rf[v * VEC + u + 2], rf[v * VEC + u + 3]};
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) s0[(r + u) * RS + k] = rf[v * VEC + u];
+        }
+      }
+    }
+  }
+};
+
+template <int MODE>
+struct AccT {
+  typedef f4 type;
+};
+template <>
+struct AccT<CF64> {
+  typedef d4 type;
+};
+
+// WM x WN waves per workgroup, each wave TM x TN blocks of 16 x 16; BK = K tile.
+template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB, int WM,
+          int WN, int TM, int TN, int BK, int MINW>
+__global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch, const int* done,
+                                                                  int nsplit, double* ws) {
+  if (done && *done) return;
+  constexpr int NT = WM * WN * 64;
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
+  typedef Stager<MODE, TA, LA, BM, BK, NT> SA;
+  typedef Stager<MODE, TB, LB, BN, BK, NT> SB;
+  typedef typename ModeTraits<MODE>::lds_t lds_t;
+  constexpr int RS = SA::RS;
+  constexpr int NBUF = MODE == CBF16X3 ? 2 : 1;  // hi + lo planes
+  typedef typename AccT<MODE>::type acc_t;
+
+  const GemmOp& op = batch.op[blockIdx.z];
+  const int tiles_m = (op.M + BM - 1) / BM, tiles_n = (op.N + BN - 1) / BN;
+  int tm, tn;
+  if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
+  const int sp = blockIdx.y;
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  __shared__ __attribute__((aligned(16))) lds_t As[2][NBUF][BM * RS];
+  __shared__ __attribute__((aligned(16))) lds_t Bs[2][NBUF][BN * RS];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  SA sa;
+  SB sb;
+  for (int seg = 0; seg < op.nseg; ++seg) {
+    int kb, ke;
+    split_range<BK>(op, seg, sp, nsplit, kb, ke);
+    if (kb >= ke) continue;
+    const void* A = op.A[seg];
+    const void* B = op.B[seg];
+    const int64_t lda = op.lda[seg], ldb = op.ldb[seg];
+    const bool va = LA == KC && (lda % SA::VEC) == 0 &&
+                    ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    const bool vb = LB == KC && (ldb % SB::VEC) == 0 &&
+                    ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    __syncthreads();  // previous segment's readers are done with the buffers
+    sa.load(A, lda, m0, op.M, kb, ke, tid, va);
+    sb.load(B, ldb, n0, op.N, kb, ke, tid, vb);
+    sa.store(As[0][0], As[0][NBUF - 1], tid);
+    sb.store(Bs[0][0], Bs[0][NBUF - 1], tid);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+      const bool more = k0 + BK < ke;
+      if (more) {
+        sa.load(A, lda, m0, op.M, k0 + BK, ke, tid, va);
+        sb.load(B, ldb, n0, op.N, k0 + BK, ke, tid, vb);
+      }
+      const lds_t* a0 = As[buf][0];
+      const lds_t* b0 = Bs[buf][0];
+      if constexpr (MODE == CBF16X3) {
+        const lds_t* a1 = As[buf][NBUF - 1];
+        const lds_t* b1 = Bs[buf][NBUF - 1];
+        const int kof = 8 * (lane >> 4);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 32) {
+          bf8 ah[TM], al[TM];
+#pragma unroll
+          for (int i = 0; i < TM; ++i) {
+            const int r = wm * TM * 16 + i * 16 + (lane & 15);
+            ah[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(a0 + r * RS + kk + kof));
+            al[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(a1 + r * RS + kk + kof));
+          }
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            const int r = wn * TN * 16 + j * 16 + (lane & 15);
+            const bf8 bh = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(b0 + r * RS + kk + kof));
+            const bf8 bl = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(b1 + r * RS + kk + kof));
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          const int kr = kk + (lane >> 4);
+          lds_t a[TM], b[TN];
+#pragma unroll
+          for (int i = 0; i < TM; ++i) a[i] = a0[(wm * TM * 16 + i * 16 + (lane & 15)) * RS + kr];
+#pragma unroll
+          for (int j = 0; j < TN; ++j) b[j] = b0[(wn * TN * 16 + j * 16 + (lane & 15)) * RS + kr];
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
+        }
+      }
+      if (more) {
+        sa.store(As[buf ^ 1][0], As[buf ^ 1][NBUF - 1], tid);
+        sb.store(Bs[buf ^ 1][0], Bs[buf ^ 1][NBUF - 1], tid);
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  const int nops = gridDim.z;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = MODE == CF64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        const int row = m0 + wm * TM * 16 + i * 16 + rr;
+        const int col = n0 + wn * TN * 16 + j * 16 + (lane & 15);
+        if (row < op.M && col < op.N) {
+          const double s = (double)acc[i][j][r];
+          if (nsplit > 1) {
+            ws[((int64_t)sp * nops + blockIdx.z) * op.M * op.N + (int64_t)row * op.N + col] = s;
+          } else {
+            double v = op.alpha * s;
+            if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
+            static_cast<TC*>(op.C)[(int64_t)row * op.ldc + col] = (TC)v;
+          }
+        }
+      }
+}
+
+// Tile shapes (macro tile M x N): 0: 128x128 (4 waves), 1: 64x64 (4 waves), 2: 256x128
+// (8 waves), 3: 128x256 (8 waves).
+constexpr int NTILES = 4;
+inline int tile_bm(int t) { return t == 1 ? 64 : (t == 2 ? 256 : 128); }
+inline int tile_bn(int t) { return t == 1 ? 64 : (t == 3 ? 256 : 128); }
+inline int tile_threads(int t) { return t >= 2 ? 512 : 256; }
+
+template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB>
+gemm_fn pick_tile(int tile) {
+  constexpr int BK = MODE == CBF16X3 ? 32 : 16;
+  switch (tile) {
+    case 0: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 4, 4, BK, 1>;
+    case 1: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 2, 2, BK, 2>;
+    case 2: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 4, 2, 4, 4, BK, 1>;
+    case 3: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 4, 4, BK, 1>;
+    default: return nullptr;
+  }
+}
+
+template <int MODE, typename TA, typename TB, typename TC, typename TX>
+gemm_fn pick_layout(int la, int lb, int tile) {
+  if (la == KC && lb == KC) return pick_tile<MODE, TA, TB, TC, TX, KC, KC>(tile);
+  if (la == KC && lb == RC) return pick_tile<MODE, TA, TB, TC, TX, KC, RC>(tile);
+  if (la == RC && lb == RC) return pick_tile<MODE, TA, TB, TC, TX, RC, RC>(tile);
+  return nullptr;
+}
+
+}  // namespace gemm_detail
+}  // namespace omm

@@ -50,7 +50,7 @@ struct GemmDesc {
   int compute;         // Compute
   int ta, tb, tc, tx;  // ElemType of A, B, C, X
   int la, lb;          // Layout of A, B
-  int tile;            // 0: 128x128 macro tile, 1: 64x64, 2: 128x64 (M x N)
+  int tile;            // macro tile (M x N): 0: 128x128, 1: 64x64, 2: 256x128, 3: 128x256
   int splitk;          // >1: K split across workgroups, partials reduced in FP64 (needs ws)
 };
 
@@ -59,6 +59,8 @@ struct GemmDesc {
 hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int* done,
                        double* ws, size_t ws_bytes, hipStream_t s);
 size_t gemm_splitk_ws_bytes(const GemmOp* ops, int nops, int splitk);
+int gemm_num_tiles();
+bool gemm_supported(const GemmDesc& d);
 
 // ---- elementwise / reduction kernels (omm_kernels.hip) ----
 // Number of per-block partial sums each reduction writes is at most RED_BLOCKS.

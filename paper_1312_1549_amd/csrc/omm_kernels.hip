@@ -25,6 +25,15 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Fixed-order sum over nb partial rows (stride w) of column c, by the whole block; result in
+// thread 0. Each thread sums a strided subset in index order, then block_sum combines them.
+__device__ __forceinline__ double sum_partials(const double* partials, int nb, int w, int c,
+                                               double* sh) {
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += NT) v += partials[b * w + c];
+  return block_sum(v, sh);
+}
+
 int red_blocks(int64_t n) {
   int64_t b = (n + NT - 1) / NT;
   if (b > RED_BLOCKS) b = RED_BLOCKS;
@@ -123,9 +132,10 @@ __global__ void k_energy_partials(const double* HW, const double* SW, int M, dou
 }
 
 __global__ void k_energy_init_final(const double* partials, int nb, DevState* st, double* trace) {
+  __shared__ double sh[NT / 64];
+  const double tr = sum_partials(partials, nb, 3, 0, sh);
+  const double f = sum_partials(partials, nb, 3, 1, sh);
   if (threadIdx.x != 0) return;
-  double tr = 0.0, f = 0.0;
-  for (int b = 0; b < nb; ++b) { tr += partials[b * 3 + 0]; f += partials[b * 3 + 1]; }
   const double E = 4.0 * tr - 2.0 * f;
   st->E = E;
   st->E_prev = E;
@@ -154,9 +164,11 @@ __global__ void k_pr_partials(const T* G, const T* PG, const T* Gp, int64_t n, i
 }
 
 __global__ void k_pr_final(const double* partials, int nb, int first, DevState* st) {
-  if (threadIdx.x != 0 || st->done) return;
-  double s1 = 0.0, s2 = 0.0;
-  for (int b = 0; b < nb; ++b) { s1 += partials[b * 2]; s2 += partials[b * 2 + 1]; }
+  if (st->done) return;
+  __shared__ double sh[NT / 64];
+  const double s1 = sum_partials(partials, nb, 2, 0, sh);
+  const double s2 = sum_partials(partials, nb, 2, 1, sh);
+  if (threadIdx.x != 0) return;
   double beta = 0.0;
   if (!first) {
     beta = (s1 - s2) / st->pg_g;
@@ -307,11 +319,11 @@ __device__ int line_minimum(const double* a, double* xout) {
 }
 
 __global__ void k_line_final(const double* partials, int nb, DevState* st) {
-  if (threadIdx.x != 0 || st->done) return;
+  if (st->done) return;
+  __shared__ double sh[NT / 64];
   double s[NCOEF];
-  for (int k = 0; k < NCOEF; ++k) s[k] = 0.0;
-  for (int b = 0; b < nb; ++b)
-    for (int k = 0; k < NCOEF; ++k) s[k] += partials[b * NCOEF + k];
+  for (int k = 0; k < NCOEF; ++k) s[k] = sum_partials(partials, nb, NCOEF, k, sh);
+  if (threadIdx.x != 0) return;
   double a[5];
   a[0] = 4.0 * s[0] - 2.0 * s[3];
   a[1] = 8.0 * s[1] - 4.0 * s[4] - 4.0 * s[5];
@@ -386,13 +398,12 @@ __global__ void k_update_mm(double* HW, double* SW, const double* H1, const doub
 
 __global__ void k_update_final(const double* partials, int nb, int M, DevState* st,
                                double* trace) {
-  if (threadIdx.x != 0 || st->done) return;
-  double tr = 0.0, f = 0.0, trs = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    tr += partials[b * 3 + 0];
-    f += partials[b * 3 + 1];
-    trs += partials[b * 3 + 2];
-  }
+  if (st->done) return;
+  __shared__ double sh[NT / 64];
+  const double tr = sum_partials(partials, nb, 3, 0, sh);
+  const double f = sum_partials(partials, nb, 3, 1, sh);
+  const double trs = sum_partials(partials, nb, 3, 2, sh);
+  if (threadIdx.x != 0) return;
   const double E_new = 4.0 * tr - 2.0 * f;
   const double E_old = st->E;
   const double diff = fabs(2.0 * (E_new - E_old)), sum = fabs(E_new + E_old);
@@ -471,7 +482,7 @@ hipError_t energy_init(const double* HW, const double* SW, int M, double* partia
                        double* trace, hipStream_t s) {
   const int nb = red_blocks((int64_t)M * M);
   hipLaunchKernelGGL(k_energy_partials, dim3(nb), dim3(NT), 0, s, HW, SW, M, partials);
-  hipLaunchKernelGGL(k_energy_init_final, dim3(1), dim3(64), 0, s, partials, nb, st, trace);
+  hipLaunchKernelGGL(k_energy_init_final, dim3(1), dim3(NT), 0, s, partials, nb, st, trace);
   return hipGetLastError();
 }
 
@@ -481,7 +492,7 @@ hipError_t beta_and_direction(const T* G, const T* PG, const T* Gprev, T* D, int
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_pr_partials<T>, dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first, partials,
                      st);
-  hipLaunchKernelGGL(k_pr_final, dim3(1), dim3(64), 0, s, partials, nb, first, st);
+  hipLaunchKernelGGL(k_pr_final, dim3(1), dim3(NT), 0, s, partials, nb, first, st);
   hipLaunchKernelGGL(k_direction<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, n, first, st);
   return hipGetLastError();
 }
@@ -497,7 +508,7 @@ hipError_t line_search(const double* HW, const double* SW, const double* H1, con
   const int nb = tile_blocks(M);
   hipLaunchKernelGGL(k_coef_partials, dim3(nb), dim3(NT), 0, s, HW, SW, H1, S1, H2, S2, M,
                      partials, st);
-  hipLaunchKernelGGL(k_line_final, dim3(1), dim3(64), 0, s, partials, nb, st);
+  hipLaunchKernelGGL(k_line_final, dim3(1), dim3(NT), 0, s, partials, nb, st);
   return hipGetLastError();
 }
 
@@ -521,7 +532,7 @@ hipError_t update_subspace(double* HW, double* SW, const double* H1, const doubl
   const int nb = tile_blocks(M);
   hipLaunchKernelGGL(k_update_mm, dim3(nb), dim3(NT), 0, s, HW, SW, H1, S1, H2, S2, M, partials,
                      st);
-  hipLaunchKernelGGL(k_update_final, dim3(1), dim3(64), 0, s, partials, nb, M, st, trace);
+  hipLaunchKernelGGL(k_update_final, dim3(1), dim3(NT), 0, s, partials, nb, M, st, trace);
   return hipGetLastError();
 }
 
