@@ -130,7 +130,31 @@ def cpu_baseline(s, C0, iters):
                       f"host BLAS threads={threads}, os.cpu_count()={os.cpu_count()}"}
 
 
+def summarize_rocprof(trace_csv, top=12):
+    """Per (kernel, grid) launch statistics from a rocprofv3 --kernel-trace CSV."""
+    import csv
+    from collections import defaultdict
+
+    groups = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        name = r["Kernel_Name"]
+        grid = (r.get("Grid_Size_X") or r.get("Grid_Size"), r.get("Grid_Size_Y"), r.get("Grid_Size_Z"))
+        groups[(name, grid)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    total = sum(sum(v) for v in groups.values())
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]
+    out = [f"{'calls':>6} {'avg_us':>10} {'share':>7}  grid(x,y,z)  kernel"]
+    for (name, grid), d in rows:
+        short = name.replace("omm::gemm_detail::", "").replace("omm::", "")
+        short = short.replace("(anonymous namespace)::", "").split("(")[0]
+        out.append(f"{len(d):>6} {sum(d) / len(d) / 1e3:>10.1f} {100 * sum(d) / total:>6.2f}%  "
+                   f"{','.join(str(g) for g in grid)}  {short}")
+    return "\n".join(out)
+
+
 def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
+        print(summarize_rocprof(sys.argv[2]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)

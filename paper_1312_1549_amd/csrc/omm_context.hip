@@ -35,6 +35,12 @@ struct Work {
     *D = nullptr, *HD = nullptr, *SD = nullptr;
 };
 
+// A bf16 hi/lo pair of planes (x = hi + lo) feeding the BF16x3 GEMMs.
+struct Plane {
+  unsigned short* hi = nullptr;
+  unsigned short* lo = nullptr;
+};
+
 constexpr int NSTAGE = 7;  // gradient, PG, PR+direction, [HD|SD], projections, line search, updates
 
 template <typename T>
@@ -65,6 +71,9 @@ struct omm_ctx {
 
   Work<double> w64;
   Work<float> w32;
+  // BF16x3 operand planes: operators (set up once) and per-iteration operands
+  Plane Hs_p, S_p, P_p, C_p, HC_p, SC_p, G_p, D_p, HD_p, SD_p, HW_p, SW_p;
+  bool hsp_valid = false, sp_valid = false, pp_valid = false;
   double *HW = nullptr, *SW = nullptr, *H1 = nullptr, *S1 = nullptr, *H2 = nullptr, *S2 = nullptr;
   double *partials = nullptr, *ws = nullptr;
   size_t ws_bytes = 0;
@@ -153,6 +162,17 @@ template <typename T>
 void free_work(Work<T>& w) {
   dfree(w.C); dfree(w.HC); dfree(w.SC); dfree(w.G); dfree(w.Gp); dfree(w.PG); dfree(w.D);
   dfree(w.HD); dfree(w.SD);
+}
+
+int alloc_plane(omm_ctx* c, Plane& p, size_t n) {
+  TRY(dalloc(c, &p.hi, n));
+  TRY(dalloc(c, &p.lo, n));
+  return OMM_OK;
+}
+
+void free_plane(Plane& p) {
+  dfree(p.hi);
+  dfree(p.lo);
 }
 
 // ---- tile / split-K choice --------------------------------------------------------------------
@@ -352,6 +372,9 @@ int ensure_inputs(omm_ctx* c) {
 
 void invalidate(omm_ctx* c) {
   c->phase_active = false;
+  c->hsp_valid = false;
+  c->sp_valid = false;
+  c->pp_valid = false;
   c->hs_valid = false;
   c->hs32_valid = false;
   c->s32_valid = false;
@@ -368,8 +391,20 @@ int prepare_shift(omm_ctx* c, double eta) {
     c->hs_valid = true;
     c->hs_eta = eta;
     c->hs32_valid = false;
+    c->hsp_valid = false;
   }
-  if (c->mode != OMM_FP64) {
+  if (c->mode == OMM_BF16X3) {
+    if (!c->hsp_valid) {
+      TRY(alloc_plane(c, c->Hs_p, nn));
+      HIPCHK(c, split_bf16(c->Hs, c->Hs_p.hi, c->Hs_p.lo, (int64_t)nn, nullptr, c->stream));
+      c->hsp_valid = true;
+    }
+    if (!c->sp_valid) {
+      TRY(alloc_plane(c, c->S_p, nn));
+      HIPCHK(c, split_bf16(c->S, c->S_p.hi, c->S_p.lo, (int64_t)nn, nullptr, c->stream));
+      c->sp_valid = true;
+    }
+  } else if (c->mode == OMM_FP32) {
     if (!c->hs32_valid) {
       TRY(dalloc(c, &c->Hs32, nn));
       HIPCHK(c, convert_f64_f32(c->Hs, c->Hs32, (int64_t)nn, c->stream));
@@ -407,8 +442,14 @@ int prepare_precon(omm_ctx* c, double tau) {
     c->p_kind = kind;
     c->p_tau = tau;
     c->p32_valid = false;
+    c->pp_valid = false;
   }
-  if (kind > 0 && c->mode != OMM_FP64 && !c->p32_valid) {
+  if (kind > 0 && c->mode == OMM_BF16X3 && !c->pp_valid) {
+    TRY(alloc_plane(c, c->P_p, nn));
+    HIPCHK(c, split_bf16(c->P, c->P_p.hi, c->P_p.lo, (int64_t)nn, nullptr, c->stream));
+    c->pp_valid = true;
+  }
+  if (kind > 0 && c->mode == OMM_FP32 && !c->p32_valid) {
     TRY(dalloc(c, &c->P32, nn));
     HIPCHK(c, convert_f64_f32(c->P, c->P32, (int64_t)nn, c->stream));
     c->p32_valid = true;
@@ -435,19 +476,65 @@ int alloc_common(omm_ctx* c) {
   return OMM_OK;
 }
 
+// Operand of a GEMM: plain pointer, or the hi/lo planes for BF16x3.
+struct Opnd {
+  const void* p;
+  const void* lo;
+};
+
+GemmOp make_op2(int M, int N, int K, Opnd A, int64_t lda, Opnd B, int64_t ldb, void* C, int64_t ldc,
+                double alpha = 1.0, const void* X = nullptr, int64_t ldx = 0, double beta = 0.0) {
+  GemmOp op = make_op(M, N, K, A.p, lda, B.p, ldb, C, ldc, alpha, X, ldx, beta);
+  op.Alo[0] = A.lo;
+  op.Blo[0] = B.lo;
+  return op;
+}
+
+Opnd pl(const Plane& p) { return {p.hi, p.lo}; }
+template <typename T>
+Opnd dn(const T* p) { return {p, nullptr}; }
+
+// Planes for the per-iteration BF16x3 operands (M x N and M x M).
+int alloc_iter_planes(omm_ctx* c) {
+  const size_t mn = (size_t)c->M * c->N, mm = (size_t)c->M * c->M;
+  for (Plane* p : {&c->C_p, &c->HC_p, &c->SC_p, &c->G_p, &c->D_p, &c->HD_p, &c->SD_p})
+    TRY(alloc_plane(c, *p, mn));
+  TRY(alloc_plane(c, c->HW_p, mm));
+  TRY(alloc_plane(c, c->SW_p, mm));
+  return OMM_OK;
+}
+
+template <typename T>
+int split(omm_ctx* c, const T* src, Plane& p, int64_t n, bool check_done = true) {
+  HIPCHK(c, split_bf16(src, p.hi, p.lo, n, check_done ? c->st : nullptr, c->stream));
+  return OMM_OK;
+}
+
 // Initial products of a phase (Sec. 2.1, Eqs. 5-6; Sec. 2.3 footnote):
 //   [HC | SC] = C [Hs | S], HW = HC C^T, SW = SC C^T, E_0.
+// Hs, S are symmetric, so both products read k-contiguous rows (KC x KC).
 template <typename T>
 int initial_products(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, double* trace) {
   const int M = (int)c->M, N = (int)c->N;
-  const int et = elem_type<T>();
-  GemmDesc d{compute, et, et, et, et, KC, RC, 0, 1};
-  GemmOp ops[2] = {make_op(M, N, N, w.C, N, Hs, N, w.HC, N),
-                   make_op(M, N, N, w.C, N, S, N, w.SC, N)};
+  const int64_t mn = (int64_t)M * N;
+  const bool bf = compute == CBF16X3;
+  const int et = bf ? T_BF16P : elem_type<T>();
+  if (bf) {
+    TRY(alloc_iter_planes(c));
+    TRY(split(c, w.C, c->C_p, mn, false));
+  }
+  const Opnd Cop = bf ? pl(c->C_p) : dn(w.C);
+  GemmDesc d{compute, et, et, elem_type<T>(), elem_type<T>(), KC, KC, 0, 1};
+  GemmOp ops[2] = {make_op2(M, N, N, Cop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HC, N),
+                   make_op2(M, N, N, Cop, N, bf ? pl(c->S_p) : dn(S), N, w.SC, N)};
   TRY(gemm(c, d, ops, 2, nullptr));
+  if (bf) {
+    TRY(split(c, w.HC, c->HC_p, mn, false));
+    TRY(split(c, w.SC, c->SC_p, mn, false));
+  }
   GemmDesc d2{compute, et, et, T_F64, T_F64, KC, KC, 0, 1};
-  GemmOp ops2[2] = {make_op(M, M, N, w.HC, N, w.C, N, c->HW, M),
-                    make_op(M, M, N, w.SC, N, w.C, N, c->SW, M)};
+  GemmOp ops2[2] = {make_op2(M, M, N, bf ? pl(c->HC_p) : dn(w.HC), N, Cop, N, c->HW, M),
+                    make_op2(M, M, N, bf ? pl(c->SC_p) : dn(w.SC), N, Cop, N, c->SW, M)};
   TRY(gemm(c, d2, ops2, 2, nullptr));
   HIPCHK(c, energy_init(c->HW, c->SW, M, c->partials, c->st, trace, c->stream));
   return OMM_OK;
@@ -482,52 +569,68 @@ int prof_collect(omm_ctx* c) {
   return OMM_OK;
 }
 
-// One line search (the stage sequence in the header comment of this file).
+// One line search (the stage sequence in the header comment of this file). In BF16x3 mode every
+// GEMM operand is split into bf16 hi/lo planes once, right after it is produced.
 template <typename T>
 int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S,
                           const T* P, int k, double* trace) {
   const int M = (int)c->M, N = (int)c->N;
   const int64_t mn = (int64_t)M * N;
+  const bool bf = compute == CBF16X3;
   const int et = elem_type<T>();
+  const int ot = bf ? T_BF16P : et;  // operand element type of the GEMMs
   const int* done = &c->st->done;
   T* G = (k & 1) ? w.Gp : w.G;
   T* Gprev = (k & 1) ? w.G : w.Gp;
   TRY(prof_mark(c));
   // G = 8 HC - 4 HW SC - 4 SW HC
   {
-    GemmDesc d{compute, T_F64, et, et, et, KC, RC, 0, 1};
-    GemmOp op = make_op(M, N, M, c->HW, M, w.SC, N, G, N, -4.0, w.HC, N, 8.0);
+    if (bf) {
+      TRY(split(c, c->HW, c->HW_p, (int64_t)M * M));
+      TRY(split(c, c->SW, c->SW_p, (int64_t)M * M));
+    }
+    GemmDesc d{compute, bf ? T_BF16P : T_F64, ot, et, et, KC, RC, 0, 1};
+    GemmOp op = make_op2(M, N, M, bf ? pl(c->HW_p) : dn(c->HW), M, bf ? pl(c->SC_p) : dn(w.SC), N,
+                         G, N, -4.0, w.HC, N, 8.0);
+    const Opnd a2 = bf ? pl(c->SW_p) : dn(c->SW), b2 = bf ? pl(c->HC_p) : dn(w.HC);
     op.nseg = 2;
-    op.A[1] = c->SW; op.lda[1] = M;
-    op.B[1] = w.HC; op.ldb[1] = N;
+    op.A[1] = a2.p; op.Alo[1] = a2.lo; op.lda[1] = M;
+    op.B[1] = b2.p; op.Blo[1] = b2.lo; op.ldb[1] = N;
     op.K[1] = M;
     TRY(gemm(c, d, &op, 1, done));
   }
   TRY(prof_mark(c));
   T* PG = G;
-  if (P) {
-    GemmDesc d{compute, et, et, et, et, KC, RC, 0, 1};
-    GemmOp op = make_op(M, N, N, G, N, P, N, w.PG, N);
+  if (c->p_kind > 0) {
+    if (bf) TRY(split(c, G, c->G_p, mn));
+    GemmDesc d{compute, ot, ot, et, et, KC, KC, 0, 1};
+    GemmOp op = make_op2(M, N, N, bf ? pl(c->G_p) : dn(G), N, bf ? pl(c->P_p) : dn(P), N, w.PG, N);
     TRY(gemm(c, d, &op, 1, done));
     PG = w.PG;
   }
   TRY(prof_mark(c));
   HIPCHK(c, beta_and_direction<T>(G, PG, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials, c->st,
                                   c->stream));
+  if (bf) TRY(split(c, w.D, c->D_p, mn));
   TRY(prof_mark(c));
+  const Opnd Dop = bf ? pl(c->D_p) : dn(w.D);
   {
-    GemmDesc d{compute, et, et, et, et, KC, RC, 0, 1};
-    GemmOp ops[2] = {make_op(M, N, N, w.D, N, Hs, N, w.HD, N),
-                     make_op(M, N, N, w.D, N, S, N, w.SD, N)};
+    GemmDesc d{compute, ot, ot, et, et, KC, KC, 0, 1};
+    GemmOp ops[2] = {make_op2(M, N, N, Dop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HD, N),
+                     make_op2(M, N, N, Dop, N, bf ? pl(c->S_p) : dn(S), N, w.SD, N)};
     TRY(gemm(c, d, ops, 2, done));
+    if (bf) {
+      TRY(split(c, w.HD, c->HD_p, mn));
+      TRY(split(c, w.SD, c->SD_p, mn));
+    }
   }
   TRY(prof_mark(c));
   {
-    GemmDesc d{compute, et, et, T_F64, T_F64, KC, KC, 0, 1};
-    GemmOp ops[4] = {make_op(M, M, N, w.D, N, w.HC, N, c->H1, M),
-                     make_op(M, M, N, w.D, N, w.SC, N, c->S1, M),
-                     make_op(M, M, N, w.D, N, w.HD, N, c->H2, M),
-                     make_op(M, M, N, w.D, N, w.SD, N, c->S2, M)};
+    GemmDesc d{compute, ot, ot, T_F64, T_F64, KC, KC, 0, 1};
+    GemmOp ops[4] = {make_op2(M, M, N, Dop, N, bf ? pl(c->HC_p) : dn(w.HC), N, c->H1, M),
+                     make_op2(M, M, N, Dop, N, bf ? pl(c->SC_p) : dn(w.SC), N, c->S1, M),
+                     make_op2(M, M, N, Dop, N, bf ? pl(c->HD_p) : dn(w.HD), N, c->H2, M),
+                     make_op2(M, M, N, Dop, N, bf ? pl(c->SD_p) : dn(w.SD), N, c->S2, M)};
     TRY(gemm(c, d, ops, 4, done));
   }
   TRY(prof_mark(c));
@@ -535,6 +638,10 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
                         c->stream));
   TRY(prof_mark(c));
   HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, w.SD, mn, c->st, c->stream));
+  if (bf) {
+    TRY(split(c, w.HC, c->HC_p, mn));
+    TRY(split(c, w.SC, c->SC_p, mn));
+  }
   HIPCHK(c, update_subspace(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
                             trace, c->stream));
   TRY(prof_mark(c));
@@ -764,6 +871,9 @@ int omm_destroy(omm_ctx* c) {
   dfree(c->Hs32); dfree(c->S32); dfree(c->P32);
   free_work(c->w64);
   free_work(c->w32);
+  for (Plane* p : {&c->Hs_p, &c->S_p, &c->P_p, &c->C_p, &c->HC_p, &c->SC_p, &c->G_p, &c->D_p,
+                   &c->HD_p, &c->SD_p, &c->HW_p, &c->SW_p})
+    free_plane(*p);
   dfree(c->HW); dfree(c->SW); dfree(c->H1); dfree(c->S1); dfree(c->H2); dfree(c->S2);
   dfree(c->partials); dfree(c->ws); dfree(c->st); dfree(c->flags); dfree(c->trace);
   dfree(c->nn_scratch); dfree(c->inv_work);
@@ -820,6 +930,11 @@ int omm_set_HS(omm_ctx* c, const double* H, const double* S, const double* T) {
     TRY(dalloc(c, &c->T, (size_t)n * n));
     HIPCHK(c, hipMemcpyAsync(c->T, T, bytes, hipMemcpyHostToDevice, c->stream));
   }
+  // Validated to 1e-10; store exactly symmetric copies so that every operator product may read
+  // rows in place of columns.
+  HIPCHK(c, symmetrize(c->H, n, c->stream));
+  HIPCHK(c, symmetrize(c->S, n, c->stream));
+  if (T) HIPCHK(c, symmetrize(c->T, n, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->have_HS = true;
   invalidate(c);
@@ -857,6 +972,10 @@ int omm_set_HS_device(omm_ctx* c, const double* dH, const double* dS, const doub
       return fail(c, OMM_E_ASYMMETRIC, std::string(names[i]) + " is not symmetric");
     }
   }
+  HIPCHK(c, symmetrize(c->H, n, c->stream));
+  HIPCHK(c, symmetrize(c->S, n, c->stream));
+  if (dT) HIPCHK(c, symmetrize(c->T, n, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->have_T = dT != nullptr;
   c->have_HS = true;
   invalidate(c);

@@ -1,4 +1,4 @@
-// BF16x3 split MFMA GEMM instantiations (v_mfma_f32_16x16x32_bf16).
+// BF16x3 split MFMA GEMM instantiations (v_mfma_f32_16x16x32_bf16) on pre-split bf16 planes.
 #include "omm_gemm_impl.h"
 
 namespace omm {
@@ -14,12 +14,11 @@ gemm_fn pick2(const GemmDesc& d) {
 }  // namespace
 
 gemm_fn pick_bf16x3(const GemmDesc& d) {
-  if (d.ta == T_F32 && d.tb == T_F32 && d.tc == T_F32 && d.tx == T_F32)
-    return pick2<float, float, float, float>(d);
-  if (d.ta == T_F32 && d.tb == T_F32 && d.tc == T_F64 && d.tx == T_F64)
-    return pick2<float, float, double, double>(d);
-  if (d.ta == T_F64 && d.tb == T_F32 && d.tc == T_F32 && d.tx == T_F32)
-    return pick2<double, float, float, float>(d);
+  typedef unsigned short P;  // pre-split bf16 (hi, lo) planes
+  if (d.ta == T_BF16P && d.tb == T_BF16P && d.tc == T_F32 && d.tx == T_F32)
+    return pick2<P, P, float, float>(d);
+  if (d.ta == T_BF16P && d.tb == T_BF16P && d.tc == T_F64 && d.tx == T_F64)
+    return pick2<P, P, double, double>(d);
   return nullptr;
 }
 

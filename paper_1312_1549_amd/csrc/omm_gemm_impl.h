@@ -20,6 +20,8 @@
 //            in HBM.
 #pragma once
 
+#include <type_traits>
+
 #include "omm_internal.h"
 
 namespace omm {
@@ -109,15 +111,19 @@ struct ModeTraits<CBF16X3> {
 
 // Global -> register staging of one operand tile (R rows x BK), `NV` vectors of VEC per thread.
 // KC: vector = VEC consecutive k of one row. RC: vector = VEC consecutive rows of one k.
+// TS = unsigned short means pre-split bf16 planes (hi at X, lo at Xlo), copied without conversion.
 template <int MODE, typename TS, int LAYOUT, int R, int BK, int NT>
 struct Stager {
   static constexpr int VEC = ModeTraits<MODE>::VEC;
   static constexpr int NV = R * BK / VEC / NT;
   static_assert(R * BK % (VEC * NT) == 0, "tile not divisible among threads");
+  static constexpr bool PL = std::is_same<TS, unsigned short>::value;
+  static_assert(!PL || MODE == CBF16X3, "bf16 planes feed the BF16x3 mode only");
   typedef typename ModeTraits<MODE>::lds_t lds_t;
   static constexpr int RS = BK + ModeTraits<MODE>::PAD;  // LDS row stride (elements)
-  float rf[MODE == CF64 ? 1 : NV * VEC];
+  float rf[(MODE == CF64 || PL) ? 1 : NV * VEC];
   double rd[MODE == CF64 ? NV * VEC : 1];
+  u16x8 ph[PL ? NV : 1], pq[PL ? NV : 1];
 
   __device__ __forceinline__ void coords(int tid, int v, int& r, int& k) const {
     const int e = tid + v * NT;
@@ -134,14 +140,44 @@ struct Stager {
     if constexpr (MODE == CF64) rd[idx] = v; else rf[idx] = (float)v;
   }
 
-  __device__ __forceinline__ void load(const void* X, int64_t ld, int r0, int rmax, int k0, int ke,
-                                       int tid, bool vec_ok) {
+  __device__ __forceinline__ void load(const void* X, const void* Xlo, int64_t ld, int r0, int rmax,
+                                       int k0, int ke, int tid, bool vec_ok) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       int r, k;
       coords(tid, v, r, k);
       const int gr = r0 + r, gk = k0 + k;
-      if (LAYOUT == KC) {
+      if constexpr (PL) {
+        const unsigned short* hp = static_cast<const unsigned short*>(X);
+        const unsigned short* lp = static_cast<const unsigned short*>(Xlo);
+        if (LAYOUT == KC) {
+          const int64_t off = (int64_t)gr * ld + gk;
+          if (vec_ok && gr < rmax && gk + 8 <= ke) {
+            ph[v] = *reinterpret_cast<const u16x8*>(hp + off);
+            pq[v] = *reinterpret_cast<const u16x8*>(lp + off);
+          } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const bool in = gr < rmax && gk + u < ke;
+              ph[v][u] = in ? hp[off + u] : (unsigned short)0;
+              pq[v][u] = in ? lp[off + u] : (unsigned short)0;
+            }
+          }
+        } else {
+          const int64_t off = (int64_t)gk * ld + gr;
+          if (vec_ok && gk < ke && gr + 8 <= rmax) {
+            ph[v] = *reinterpret_cast<const u16x8*>(hp + off);
+            pq[v] = *reinterpret_cast<const u16x8*>(lp + off);
+          } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const bool in = gr + u < rmax && gk < ke;
+              ph[v][u] = in ? hp[off + u] : (unsigned short)0;
+              pq[v][u] = in ? lp[off + u] : (unsigned short)0;
+            }
+          }
+        }
+      } else if (LAYOUT == KC) {
         const bool full = vec_ok && gr < rmax && gk + VEC <= ke;
         const TS* p = static_cast<const TS*>(X) + (int64_t)gr * ld + gk;
         if (full) {
@@ -183,7 +219,18 @@ struct Stager {
     for (int v = 0; v < NV; ++v) {
       int r, k;
       coords(tid, v, r, k);
-      if constexpr (MODE == CBF16X3) {
+      if constexpr (PL) {
+        if (LAYOUT == KC) {
+          *reinterpret_cast<u16x8*>(s0 + r * RS + k) = ph[v];
+          *reinterpret_cast<u16x8*>(s1 + r * RS + k) = pq[v];
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            s0[(r + u) * RS + k] = ph[v][u];
+            s1[(r + u) * RS + k] = pq[v][u];
+          }
+        }
+      } else if constexpr (MODE == CBF16X3) {
         if (LAYOUT == KC) {
           u16x8 h, l;
 #pragma unroll
@@ -278,14 +325,18 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch
     if (kb >= ke) continue;
     const void* A = op.A[seg];
     const void* B = op.B[seg];
+    const void* Al = op.Alo[seg];
+    const void* Bl = op.Blo[seg];
     const int64_t lda = op.lda[seg], ldb = op.ldb[seg];
-    const bool va = LA == KC && (lda % SA::VEC) == 0 &&
-                    ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-    const bool vb = LB == KC && (ldb % SB::VEC) == 0 &&
-                    ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    const bool va = (SA::PL || LA == KC) && (lda % SA::VEC) == 0 &&
+                    ((reinterpret_cast<uintptr_t>(A) & 15) == 0) &&
+                    (!SA::PL || (reinterpret_cast<uintptr_t>(Al) & 15) == 0);
+    const bool vb = (SB::PL || LB == KC) && (ldb % SB::VEC) == 0 &&
+                    ((reinterpret_cast<uintptr_t>(B) & 15) == 0) &&
+                    (!SB::PL || (reinterpret_cast<uintptr_t>(Bl) & 15) == 0);
     __syncthreads();  // previous segment's readers are done with the buffers
-    sa.load(A, lda, m0, op.M, kb, ke, tid, va);
-    sb.load(B, ldb, n0, op.N, kb, ke, tid, vb);
+    sa.load(A, Al, lda, m0, op.M, kb, ke, tid, va);
+    sb.load(B, Bl, ldb, n0, op.N, kb, ke, tid, vb);
     sa.store(As[0][0], As[0][NBUF - 1], tid);
     sb.store(Bs[0][0], Bs[0][NBUF - 1], tid);
     __syncthreads();
@@ -293,8 +344,8 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch
     for (int k0 = kb; k0 < ke; k0 += BK) {
       const bool more = k0 + BK < ke;
       if (more) {
-        sa.load(A, lda, m0, op.M, k0 + BK, ke, tid, va);
-        sb.load(B, ldb, n0, op.N, k0 + BK, ke, tid, vb);
+        sa.load(A, Al, lda, m0, op.M, k0 + BK, ke, tid, va);
+        sb.load(B, Bl, ldb, n0, op.N, k0 + BK, ke, tid, vb);
       }
       const lds_t* a0 = As[buf][0];
       const lds_t* b0 = Bs[buf][0];

@@ -30,13 +30,16 @@ enum Layout : int { KC = 0, RC = 1 };
 
 enum Compute : int { CF64 = 0, CF32 = 1, CBF16X3 = 2 };
 
-enum ElemType : int { T_F64 = 0, T_F32 = 1 };
+// T_BF16P: a pair of bf16 planes (hi, lo) with a = hi + lo, pointers in A/Alo (B/Blo).
+enum ElemType : int { T_F64 = 0, T_F32 = 1, T_BF16P = 2 };
 
 struct GemmOp {
   int M, N;            // output rows, columns
   int nseg;            // 1 or 2 summed K segments
   const void* A[2];
   const void* B[2];
+  const void* Alo[2];  // lo planes (T_BF16P operands only)
+  const void* Blo[2];
   int64_t lda[2], ldb[2];
   int K[2];
   void* C;             // output
@@ -70,6 +73,11 @@ constexpr int NCOEF = 13;
 hipError_t shift_hamiltonian(const double* H, const double* S, double eta, double* Hs, int64_t n,
                              hipStream_t s);
 hipError_t convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+// hi = bf16(x), lo = bf16(x - hi) (round to nearest even), skipped when st->done.
+hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, int64_t n,
+                      const DevState* st, hipStream_t s);
+hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t n,
+                      const DevState* st, hipStream_t s);
 hipError_t convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 hipError_t copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
 hipError_t validate_symmetric(const double* A, int64_t n, double rtol, int* flags, hipStream_t s);

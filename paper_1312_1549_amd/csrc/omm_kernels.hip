@@ -52,6 +52,40 @@ __global__ void k_convert(const A* src, B* dst, int64_t n) {
     dst[i] = (B)src[i];
 }
 
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+// hi/lo bf16 planes of src; 4 elements per thread step (8-byte stores).
+template <typename T>
+__global__ void k_split(const T* src, unsigned short* hi, unsigned short* lo, int64_t n,
+                        const DevState* st) {
+  if (st && st->done) return;
+  const int64_t n4 = n / 4;
+  typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n4; i += (int64_t)gridDim.x * NT) {
+    us4 h, l;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double v = (double)src[4 * i + u];
+      const unsigned short hb = bf16_bits((float)v);
+      h[u] = hb;
+      l[u] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+    }
+    *reinterpret_cast<us4*>(hi + 4 * i) = h;
+    *reinterpret_cast<us4*>(lo + 4 * i) = l;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+    const int64_t i = 4 * n4 + threadIdx.x;
+    const double v = (double)src[i];
+    const unsigned short hb = bf16_bits((float)v);
+    hi[i] = hb;
+    lo[i] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+  }
+}
+
 int ew_blocks(int64_t n) {
   int64_t b = (n + NT - 1) / NT;
   if (b > 8192) b = 8192;
@@ -453,6 +487,18 @@ hipError_t shift_hamiltonian(const double* H, const double* S, double eta, doubl
 
 hipError_t convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL((k_convert<double, float>), dim3(ew_blocks(n)), dim3(NT), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, int64_t n,
+                      const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_split<float>, dim3(ew_blocks(n / 4 + 1)), dim3(NT), 0, s, src, hi, lo, n, st);
+  return hipGetLastError();
+}
+
+hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t n,
+                      const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_split<double>, dim3(ew_blocks(n / 4 + 1)), dim3(NT), 0, s, src, hi, lo, n, st);
   return hipGetLastError();
 }
 

@@ -59,7 +59,9 @@ def test_autograd_backward_c5(torch, c5):
     E.backward()
     gH, gS = H.grad.cpu().numpy(), S.grad.cpu().numpy()
     print(f"refined: rel err dE/dH {_rel(gH, gH_ref):.2e} dE/dS {_rel(gS, gS_ref):.2e}")
-    assert _rel(gH, gH_ref) < 1e-5 and _rel(gS, gS_ref) < 1e-5
+    # The derivatives are first order in the error of C, the energy second order: with a gap of
+    # 1.3e-3 at the Fermi level, an FP64 minimum converged to tol 1e-14 leaves ~1e-5 in C.
+    assert _rel(gH, gH_ref) < 5e-5 and _rel(gS, gS_ref) < 5e-5
 
     # FP32 forward alone: gradients at the FP32 minimizer (error set by the 1.3e-3 gap)
     H.grad = None
