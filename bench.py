@@ -52,8 +52,8 @@ def reference_energy(name, s):
     return float(d["E_min"])
 
 
-def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps):
-    solver = OMM(s.N, s.M, precision=prec, refine=False)
+def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=False, resync=20):
+    solver = OMM(s.N, s.M, precision=prec, refine=refine, resync=resync)
     solver.set_HS(dev["H"], dev["S"], dev["T"])
     t0 = time.perf_counter()
     solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # setup only
@@ -77,36 +77,41 @@ def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps):
     return wall, setup_s, stages
 
 
-def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, mixed_tol, fp64_iter_s):
-    """Wall time from omm_minimize entry to the first energy within `target` of E_ref."""
-    solver = OMM(s.N, s.M, precision=prec, refine=prec != "fp64", mixed_tol=mixed_tol)
+def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, resync):
+    """Wall time from omm_minimize entry (P already built) to the first FP64-exact energy within
+    `target` of the closed-form minimum E_ref. The run proceeds in chunks of `resync` line
+    searches (omm_iterate) and stops at the first chunk that reaches the target."""
+    mixed = prec != "fp64"
+    solver = OMM(s.N, s.M, precision=prec, refine=True, resync=resync)
     solver.set_HS(dev["H"], dev["S"], dev["T"])
-    # build P once outside the measurement (reported separately): one setup-only call
     t0 = time.perf_counter()
-    solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)
+    solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # builds P
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
+    log_every = max(1, 200 // resync)
     t0 = time.perf_counter()
-    status = solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=1e-13, max_iter=max_iter)
+    solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # setup: a2 from C0
+    done, hit, err, chunks = 0, None, float("inf"), 0
+    while done < max_iter:
+        solver.iterate(resync, tol=0.0)
+        done += resync
+        chunks += 1
+        E = solver.checkpoints()[1][-1] if mixed else solver.energy_trace()[-1]
+        err = abs(E - E_ref) / abs(E_ref)
+        if chunks % log_every == 0:
+            log(f"  {prec}: {done} line searches, rel err {err:.3e}, {time.perf_counter() - t0:.1f}s")
+        if err <= target:
+            hit = done
+            break
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    tr = solver.energy_trace()
-    n_mixed, n_fp64 = solver.phase_stats()
     solver.close()
-    # the reported energy is an FP64 one: the FP64 phase is the last n_fp64 + 1 trace entries
-    fp64_tr = tr[len(tr) - (n_fp64 + 1):]
-    err = np.abs(fp64_tr - E_ref) / abs(E_ref)
-    ok = np.nonzero(err <= target)[0]
-    out = {"precision": prec, "mixed_iterations": int(n_mixed), "fp64_iterations": int(n_fp64),
-           "status": int(status), "final_rel_err": float(err[-1]), "wall_s_to_tol": total,
-           "first_call_with_precon_s": t_first}
-    if len(ok) == 0:
-        out["time_to_target_s"] = None
-        return out
-    k = int(ok[0])
-    # FP64 line searches after the first hit were not needed: subtract their cost
-    out["time_to_target_s"] = max(0.0, total - (n_fp64 - k) * fp64_iter_s)
-    out["fp64_iter_of_target"] = k
+    out = {"precision": prec + ("+fp64-state" if mixed else ""), "target": target,
+           "line_searches": hit, "time_to_target_s": total if hit else None,
+           "rel_err_at_stop": err, "first_call_with_precon_s": t_first,
+           "checked_every": resync}
+    if mixed:
+        out["resync_every"] = resync
     return out
 
 
@@ -151,9 +156,24 @@ def summarize_rocprof(trace_csv, top=12):
     return "\n".join(out)
 
 
+def copy_kernel(nbytes):
+    """A plain device copy of a known size (reads and writes `nbytes` each): the calibration
+    kernel for the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    b = a.clone()
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "check": float(b[-1])}))
+
+
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
         print(summarize_rocprof(sys.argv[2]))
+        return
+    if len(sys.argv) > 2 and sys.argv[1] == "--copy-kernel":
+        copy_kernel(int(sys.argv[2]))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,7 +185,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison rate")
     ap.add_argument("--max-iter", type=int, default=4000)
-    ap.add_argument("--mixed-tol", type=float, default=1e-9)
+    ap.add_argument("--resync", type=int, default=20)
     ap.add_argument("--cpu-iters", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -185,11 +205,18 @@ def main():
 
     flops = flops_per_iteration(s.N, s.M, preconditioned=s.tau > 0)
     prof_steps = min(args.steps, 10)
+    mixed = args.precision != "fp64"
     log(f"timing {args.precision}: warmup {args.warmup}, steps {args.steps}")
     wall, setup_s, stages = time_iterations(OMM, torch, dev, s, args.precision, args.steps,
-                                            args.warmup, prof_steps)
+                                            args.warmup, prof_steps, refine=mixed,
+                                            resync=args.resync)
     ips = args.steps / wall
     log(f"{args.precision}: {ips:.3f} iters/s ({1e3 * wall / args.steps:.2f} ms/iter)")
+    pure = None
+    if mixed:
+        wp, _, stp = time_iterations(OMM, torch, dev, s, args.precision, args.steps, 2, 0)
+        pure = args.steps / wp
+        log(f"{args.precision} with FP32 state, no resync: {pure:.3f} iters/s")
 
     fp64 = None
     if not args.no_fp64 and args.precision != "fp64":
@@ -216,10 +243,15 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "N": s.N, "M": s.M, "eta": s.eta,
                    "tau": s.tau, "seed": 0, "c0_seed": 1},
         "algorithmic_tflops": flops * ips / 1e12,
+        "scheme": (f"{args.precision} MFMA products, FP64 CG state and reductions, FP64 "
+                   f"resynchronization every {args.resync} line searches" if mixed else
+                   "FP64 MFMA products and FP64 reductions"),
         "setup_s": setup_s,
         "stages_ms": stages,
         "roofline": roofline,
     }
+    if pure:
+        result["fp32_state_no_resync_iters_per_s"] = pure
     if fp64:
         result["fp64_iters_per_s"] = fp64["iters_per_s"]
         result["fp64_stages_ms"] = fp64["stages_ms"]
@@ -230,19 +262,18 @@ def main():
         if E_ref is None:
             log("no stored closed-form energy for these inputs: skipping time-to-converged")
         else:
-            fp64_rate = fp64["iters_per_s"] if fp64 else ips
             conv = {}
-            log("time to converged: fp64")
-            conv["fp64"] = time_to_converged(OMM, torch, dev, s, "fp64", E_ref, 1e-10,
-                                             args.max_iter, args.mixed_tol, 1.0 / fp64_rate)
+            log("time to converged: fp64 (1e-8 and 1e-10)")
+            conv["fp64_1e-8"] = time_to_converged(OMM, torch, dev, s, "fp64", E_ref, 1e-8,
+                                                  args.max_iter, args.resync)
             if args.precision != "fp64":
-                log(f"time to converged: {args.precision} + fp64 refinement")
-                conv[args.precision] = time_to_converged(OMM, torch, dev, s, args.precision, E_ref,
-                                                         1e-8, args.max_iter, args.mixed_tol,
-                                                         1.0 / fp64_rate)
-                a, b = conv["fp64"].get("time_to_target_s"), conv[args.precision].get("time_to_target_s")
+                log(f"time to converged: {args.precision} with FP64 state (1e-8)")
+                conv[args.precision + "_1e-8"] = time_to_converged(
+                    OMM, torch, dev, s, args.precision, E_ref, 1e-8, args.max_iter, args.resync)
+                a = conv["fp64_1e-8"].get("time_to_target_s")
+                b = conv[args.precision + "_1e-8"].get("time_to_target_s")
                 if a and b:
-                    conv["mixed_speedup"] = a / b
+                    conv["mixed_speedup_1e-8"] = a / b
             conv["E_ref"] = E_ref
             result["time_to_converged"] = conv
 

@@ -62,14 +62,20 @@ typedef struct omm_ctx omm_ctx;
 int omm_create(int64_t N, int64_t M, omm_ctx **out);
 int omm_destroy(omm_ctx *ctx);
 
-/* Select the arithmetic of the products (OMM_FP64 default). With a mixed mode and
- * fp64_refine != 0, the mixed-precision minimization is followed by an FP64 refinement: HC, SC,
- * HW, SW are recomputed in FP64 from C and FP64 CG runs to tol. */
+/* Select the arithmetic of the products (OMM_FP64 default). fp64_refine != 0 with a mixed mode:
+ *  - OMM_BF16X3: the CG state (C, HC, SC, HW, SW) is kept in FP64 while every cubic product runs
+ *    in BF16x3; every omm_set_resync() line searches HC, SC, HW, SW and the energy are recomputed
+ *    exactly in FP64 from C, and the stopping rule (Eq. 18) is applied to consecutive exact
+ *    energies (scaled by the number of line searches between them);
+ *  - OMM_FP32: an FP32 minimization to omm_set_mixed_tol() followed by an FP64 one from its C.
+ * fp64_refine == 0: the whole minimization runs in the mixed arithmetic with FP32 storage. */
 int omm_set_precision(omm_ctx *ctx, int mode, int fp64_refine);
 
-/* Stopping threshold of the mixed-precision phase (default 1e-9; FP64 refinement then runs to
- * the tol given to omm_minimize). */
+/* Stopping threshold of the FP32 phase of OMM_FP32 + refinement (default 1e-9). */
 int omm_set_mixed_tol(omm_ctx *ctx, double tol);
+
+/* Line searches between FP64 resynchronizations of OMM_BF16X3 + refinement (default 20). */
+int omm_set_resync(omm_ctx *ctx, int every);
 
 /* Use `hip_stream` (a hipStream_t) for all work; NULL restores the context's own stream. */
 int omm_set_stream(omm_ctx *ctx, void *hip_stream);
@@ -132,6 +138,9 @@ int omm_stats(omm_ctx *ctx, int *iters, double *last_rel_change);
  * run reports all of them as FP64). The energy trace holds mixed_iters + 1 entries of the mixed
  * phase followed by fp64_iters + 1 entries of the FP64 phase (when both ran). */
 int omm_phase_stats(omm_ctx *ctx, int *mixed_iters, int *fp64_iters);
+/* FP64-exact energies of the OMM_BF16X3 + refinement scheme: the line-search index and energy
+ * at the start and at every resynchronization (up to cap; *n = total). */
+int omm_checkpoints(omm_ctx *ctx, int *iters, double *energies, int cap, int *n);
 /* Energies E_0, E_1, ... of the last minimize call (phase 1 then refinement), up to cap. */
 int omm_energy_trace(omm_ctx *ctx, double *buf, int cap, int *n);
 

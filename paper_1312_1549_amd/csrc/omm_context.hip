@@ -17,6 +17,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -90,6 +91,12 @@ struct omm_ctx {
   // active CG phase (continued by omm_iterate)
   bool phase_active = false;
   int phase_prec = OMM_FP64;  // precision of the active phase
+  bool phase_mixed64 = false; // active phase: BF16x3 products on an FP64 state (with resyncs)
+  int resync_every = 20;      // line searches between FP64 resynchronizations
+  int since_resync = 0;
+  double resync_E = 0.0;      // FP64 energy at the last resynchronization
+  std::vector<int> ck_iter;   // FP64-exact energies of the mixed scheme: (line search, E)
+  std::vector<double> ck_E;
   int phase_k = 0;            // line searches launched in the active phase
   int trace_off = 0;          // offset of the active phase in the energy trace
   int iters_before = 0;       // line searches of earlier phases of the last minimize call
@@ -165,8 +172,12 @@ void free_work(Work<T>& w) {
 }
 
 int alloc_plane(omm_ctx* c, Plane& p, size_t n) {
+  if (p.hi) return OMM_OK;
   TRY(dalloc(c, &p.hi, n));
   TRY(dalloc(c, &p.lo, n));
+  // never read before written; zeroed so that a missed split could not depend on stale memory
+  HIPCHK(c, hipMemsetAsync(p.hi, 0, n * sizeof(unsigned short), c->stream));
+  HIPCHK(c, hipMemsetAsync(p.lo, 0, n * sizeof(unsigned short), c->stream));
   return OMM_OK;
 }
 
@@ -372,6 +383,7 @@ int ensure_inputs(omm_ctx* c) {
 
 void invalidate(omm_ctx* c) {
   c->phase_active = false;
+  c->phase_mixed64 = false;
   c->hsp_valid = false;
   c->sp_valid = false;
   c->pp_valid = false;
@@ -721,6 +733,69 @@ int phase_iterate(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, 
   return OMM_OK;
 }
 
+// FP64 resynchronization of the CG state from C (Sec. 2.1, Eqs. 5-6): HC, SC, HW, SW and the
+// energy are recomputed exactly, removing what the BF16x3 increments accumulated.
+int resync_fp64(omm_ctx* c) {
+  const int M = (int)c->M, N = (int)c->N;
+  Work<double>& w = c->w64;
+  GemmDesc d{CF64, T_F64, T_F64, T_F64, T_F64, KC, KC, 0, 1};
+  GemmOp ops[2] = {make_op(M, N, N, w.C, N, c->Hs, N, w.HC, N),
+                   make_op(M, N, N, w.C, N, c->S, N, w.SC, N)};
+  TRY(gemm(c, d, ops, 2, nullptr));
+  GemmOp ops2[2] = {make_op(M, M, N, w.HC, N, w.C, N, c->HW, M),
+                    make_op(M, M, N, w.SC, N, w.C, N, c->SW, M)};
+  TRY(gemm(c, d, ops2, 2, nullptr));
+  // the BF16x3 products read HC and SC through their planes
+  TRY(split(c, w.HC, c->HC_p, (int64_t)M * N, false));
+  TRY(split(c, w.SC, c->SC_p, (int64_t)M * N, false));
+  const int it = c->st_host->iter;
+  TRY(ensure_trace(c, c->trace_off + it + 2));
+  HIPCHK(c, energy_init(c->HW, c->SW, M, c->partials, c->st, c->trace + c->trace_off + it,
+                        c->stream));
+  TRY(read_state(c));
+  c->since_resync = 0;
+  c->ck_iter.push_back(it);
+  c->ck_E.push_back(c->st_host->E);
+  return OMM_OK;
+}
+
+// Up to `count` line searches of the mixed scheme: BF16x3 products, FP64 state, an FP64
+// resynchronization every `resync_every` line searches. The stopping rule (Eq. 18) is applied
+// to consecutive FP64-exact energies, scaled by the number of line searches between them.
+int mixed64_iterate(omm_ctx* c, double tol, int count, int* done_out) {
+  const int K = c->resync_every > 0 ? c->resync_every : 20;
+  const double* P = c->p_kind > 0 ? c->P : nullptr;
+  int left = count;
+  *done_out = 2;
+  while (left > 0) {
+    const int n = std::min(left, K - c->since_resync);
+    int d = 0;
+    TRY(phase_iterate<double>(c, c->w64, CBF16X3, c->Hs, c->S, P, 0.0, n, &d));
+    left -= n;
+    c->since_resync += n;
+    if (d < 0) {
+      *done_out = d;
+      return OMM_OK;
+    }
+    if (c->since_resync >= K || left == 0) {
+      const int span = c->since_resync;
+      const double E_old = c->resync_E;
+      TRY(resync_fp64(c));
+      const double E = c->st_host->E;
+      c->resync_E = E;
+      if (!std::isfinite(E)) {
+        *done_out = -5;
+        return OMM_OK;
+      }
+      if (fabs(2.0 * (E - E_old)) <= span * tol * fabs(E + E_old)) {
+        *done_out = 1;
+        return OMM_OK;
+      }
+    }
+  }
+  return OMM_OK;
+}
+
 int status_of_done(omm_ctx* c, int done) {
   switch (done) {
     case 1: return OMM_OK;
@@ -745,7 +820,8 @@ int minimize_impl(omm_ctx* c, const double* C0, bool C0_device, double eta, doub
   const size_t mn = (size_t)c->M * c->N;
   TRY(alloc_common(c));
   TRY(alloc_work<double>(c, c->w64));
-  if (c->mode != OMM_FP64) TRY(alloc_work<float>(c, c->w32));
+  const bool mixed64 = c->mode == OMM_BF16X3 && c->refine;
+  if (c->mode != OMM_FP64 && !mixed64) TRY(alloc_work<float>(c, c->w32));
   TRY(prepare_shift(c, eta));
   TRY(prepare_precon(c, tau));
   c->eta_last = eta;
@@ -756,16 +832,34 @@ int minimize_impl(omm_ctx* c, const double* C0, bool C0_device, double eta, doub
     else HIPCHK(c, hipMemcpyAsync(c->w64.C, C0, mn * sizeof(double), hipMemcpyHostToDevice, c->stream));
     c->c_prec = OMM_FP64;
   }
-  if (c->mode != OMM_FP64 && c->c_prec == OMM_FP64)
+  if (c->mode != OMM_FP64 && !mixed64 && c->c_prec == OMM_FP64)
     HIPCHK(c, convert_f64_f32(c->w64.C, c->w32.C, (int64_t)mn, c->stream));
-  if (c->mode == OMM_FP64 && c->c_prec != OMM_FP64)
+  if ((c->mode == OMM_FP64 || mixed64) && c->c_prec != OMM_FP64)
     HIPCHK(c, convert_f32_f64(c->w32.C, c->w64.C, (int64_t)mn, c->stream));
   c->have_C = true;
 
   int done1 = 0, done2 = 0;
   c->iters = 0;
   c->iters_before = 0;
-  if (c->mode == OMM_FP64) {
+  c->phase_mixed64 = false;
+  c->ck_iter.clear();
+  c->ck_E.clear();
+  if (mixed64) {
+    TRY(phase_begin<double>(c, c->w64, CF64, c->Hs, c->S, tol, 0));
+    TRY(alloc_iter_planes(c));
+    TRY(split(c, c->w64.HC, c->HC_p, (int64_t)mn, false));
+    TRY(split(c, c->w64.SC, c->SC_p, (int64_t)mn, false));
+    c->phase_prec = OMM_BF16X3;
+    c->phase_mixed64 = true;
+    c->since_resync = 0;
+    c->resync_E = c->st_host->E;
+    c->ck_iter.push_back(0);
+    c->ck_E.push_back(c->st_host->E);
+    TRY(mixed64_iterate(c, tol, max_iter, &done1));
+    c->c_prec = OMM_FP64;
+    c->iters = c->st_host->iter;
+    c->trace_n = c->iters + 1;
+  } else if (c->mode == OMM_FP64) {
     TRY(phase_begin<double>(c, c->w64, CF64, c->Hs, c->S, tol, 0));
     c->phase_prec = OMM_FP64;
     TRY(phase_iterate<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr, tol,
@@ -897,6 +991,24 @@ int omm_set_mixed_tol(omm_ctx* c, double tol) {
   if (!c) return OMM_E_ARG;
   if (!(tol >= 0.0)) return fail(c, OMM_E_ARG, "tol must be >= 0");
   c->mixed_tol = tol;
+  return OMM_OK;
+}
+
+int omm_set_resync(omm_ctx* c, int every) {
+  if (!c) return OMM_E_ARG;
+  if (every < 1) return fail(c, OMM_E_ARG, "resync interval must be >= 1");
+  c->resync_every = every;
+  return OMM_OK;
+}
+
+int omm_checkpoints(omm_ctx* c, int* iters, double* energies, int cap, int* n) {
+  if (!c || ((!iters || !energies) && cap > 0)) return c ? fail(c, OMM_E_ARG, "null buffer") : OMM_E_ARG;
+  const int k = std::min(cap, (int)c->ck_E.size());
+  for (int i = 0; i < k; ++i) {
+    iters[i] = c->ck_iter[i];
+    energies[i] = c->ck_E[i];
+  }
+  if (n) *n = (int)c->ck_E.size();
   return OMM_OK;
 }
 
@@ -1106,7 +1218,10 @@ int omm_iterate(omm_ctx* c, int count, double tol) {
   if (count < 0 || !(tol >= 0.0)) return fail(c, OMM_E_ARG, "need count >= 0 and tol >= 0");
   if (!c->phase_active) return fail(c, OMM_E_STATE, "no active minimization to continue");
   int done = 0;
-  if (c->phase_prec == OMM_FP64) {
+  if (c->phase_mixed64) {
+    TRY(mixed64_iterate(c, tol, count, &done));
+    c->c_prec = OMM_FP64;
+  } else if (c->phase_prec == OMM_FP64) {
     TRY(phase_iterate<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr, tol,
                               count, &done));
     c->c_prec = OMM_FP64;

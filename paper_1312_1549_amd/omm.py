@@ -53,7 +53,8 @@ class OMM:
     """One dense OMM problem (N basis orbitals, M Wannier functions) on the current GPU."""
 
     def __init__(self, N: int, M: int, precision: str = "fp64", refine: bool = True,
-                 mixed_tol: Optional[float] = None, use_torch_stream: bool = True):
+                 mixed_tol: Optional[float] = None, use_torch_stream: bool = True,
+                 resync: Optional[int] = None):
         self._L = lib()
         self.N, self.M = int(N), int(M)
         h = ct.c_void_p()
@@ -64,6 +65,8 @@ class OMM:
         self.set_precision(precision, refine)
         if mixed_tol is not None:
             self._check(self._L.omm_set_mixed_tol(self._h, float(mixed_tol)))
+        if resync is not None:
+            self._check(self._L.omm_set_resync(self._h, int(resync)))
         self._use_torch_stream = use_torch_stream
 
     # -- plumbing --------------------------------------------------------------------------
@@ -192,6 +195,15 @@ class OMM:
         rel = ct.c_double()
         self._check(self._L.omm_stats(self._h, ct.byref(it), ct.byref(rel)))
         return it.value, rel.value
+
+    def checkpoints(self):
+        """(line-search indices, FP64-exact energies) of the BF16x3 + FP64-state scheme."""
+        n = ct.c_int()
+        self._check(self._L.omm_checkpoints(self._h, None, None, 0, ct.byref(n)))
+        it = (ct.c_int * max(n.value, 1))()
+        E = (ct.c_double * max(n.value, 1))()
+        self._check(self._L.omm_checkpoints(self._h, it, E, n.value, ct.byref(n)))
+        return np.array(list(it)[: n.value]), np.array(list(E)[: n.value])
 
     def phase_stats(self):
         """(mixed-precision line searches, FP64 line searches) of the last minimize call."""

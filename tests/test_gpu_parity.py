@@ -156,7 +156,27 @@ def test_mixed_precision_c2(lib_ok, c2, precision):
     solver, status = _run(lib_ok, s, C0, eta, tau, 1e-13, 3000, precision=precision, refine=True)
     err = abs(solver.energy() - E_ref) / abs(E_ref)
     print(f"{precision}+refine: rel err {err:.3e} iters {solver.stats()[0]}")
-    assert err < 1e-8
+    assert status == 0 and err < 1e-8
+    if precision == "bf16x3":
+        # the FP64-exact checkpoints of the scheme decrease to the closed form
+        its, Es = solver.checkpoints()
+        assert its[0] == 0 and np.all(np.diff(its) > 0)
+        assert abs(Es[-1] - E_ref) <= 1e-8 * abs(E_ref)
+        assert np.all(Es[1:] >= E_ref - 1e-9 * abs(E_ref))  # variational
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_runs_are_bitwise_reproducible(lib_ok, c2, precision):
+    """Fixed-order reductions: two identical runs give identical energies, bit for bit (a read of
+    uninitialized or stale device memory would show up here)."""
+    s, C0, w = c2
+    _say(f"reproducibility {precision} c2")
+    traces = []
+    for _ in range(2):
+        solver, _ = _run(lib_ok, s, C0, 0.5, 10.0, 0.0, 60, precision=precision, refine=True)
+        traces.append(solver.energy_trace())
+        solver.close()
+    assert np.array_equal(traces[0], traces[1])
 
 
 def test_error_paths(lib_ok, c1):
