@@ -1,24 +1,350 @@
-// Batched entry points: many independent (H, S) systems of uneven size.
+// Batched entry points: many independent (H, S) systems of uneven size in one set of launches.
 //
-// Each system gets its own context on a shared stream; systems are minimized one after
-// another with the FP32 MFMA plan. This is the correctness baseline of the batched interface.
+// Every CG stage is one launch over all systems. The products are grouped persistent GEMMs that
+// walk the concatenated tile lists of all systems (FP32 MFMA, a system that has stopped is
+// skipped through its device flag); the reductions, the line minimum and the updates are grouped
+// kernels with one y-slice per system (FP64 accumulation). The first line search runs eagerly
+// and autotunes the macro tile of each grouped product; then two line searches are captured in
+// a hipGraph and the graph is replayed until every system has stopped. Setup (shift,
+// preconditioner inverse, FP32 copies) is per system.
+#include <math.h>
+
 #include <string>
 #include <vector>
 
 #include "../../include/omm.h"
+#include "omm_internal.h"
+
+using namespace omm;
+
+namespace {
+
+struct BSys {
+  int64_t N = 0, M = 0;
+  double *H = nullptr, *S = nullptr, *T = nullptr;  // FP64 inputs
+  bool have_T = false, have_HS = false;
+  double *Hs64 = nullptr, *P64 = nullptr, *C64 = nullptr;
+  float *Hs = nullptr, *S32 = nullptr, *P = nullptr;
+  float *C = nullptr, *HC = nullptr, *SC = nullptr, *G0 = nullptr, *G1 = nullptr, *PG = nullptr,
+        *D = nullptr, *HD = nullptr, *SD = nullptr;
+  double *HW = nullptr, *SW = nullptr, *H1 = nullptr, *S1 = nullptr, *H2 = nullptr, *S2 = nullptr;
+  double* partials = nullptr;
+  double* trace = nullptr;
+  int trace_cap = 0;
+  int p_kind = -1;  // -1 not built, 0 none, 1 S^-1, 2 (S + T/tau)^-1
+  double p_tau = 0.0;
+  bool have_C = false;
+};
+
+// One grouped product: host op list, device copies, chosen macro tile.
+struct OpList {
+  GemmDesc d{};
+  std::vector<GemmOp> ops;
+  std::vector<const int*> done;
+  GemmOp* d_ops = nullptr;
+  int* d_tiles = nullptr;
+  const int** d_done = nullptr;
+  int cap = 0;
+  int grid = 0;
+  bool tuned = false;
+};
+
+}  // namespace
 
 struct omm_batch {
-  std::vector<omm_ctx*> sys;
+  std::vector<BSys> sys;
+  hipStream_t stream = nullptr;
+  DevState* st = nullptr;       // nsys, device
+  DevState* st_host = nullptr;  // nsys, pinned
+  SysDev* d_sys = nullptr;
+  double* inv_work = nullptr;
+  size_t inv_cap = 0;
+  OpList init1, init2, grad[2], pg[2], hdsd, proj;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   std::vector<int> iters;
   std::vector<double> E;
   std::string err;
 };
 
 namespace {
+
 int bfail(omm_batch* b, int code, const std::string& m) {
   if (b) b->err = m;
   return code;
 }
+
+#define BHIP(b, x)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return bfail(b, OMM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define BTRY(x)                  \
+  do {                           \
+    int r_ = (x);                \
+    if (r_ != OMM_OK) return r_; \
+  } while (0)
+
+template <typename P>
+int balloc(omm_batch* b, P** p, size_t n) {
+  if (*p) return OMM_OK;
+  if (hipMalloc((void**)p, (n ? n : 1) * sizeof(P)) != hipSuccess) {
+    *p = nullptr;
+    return bfail(b, OMM_E_ALLOC, "hipMalloc failed");
+  }
+  return OMM_OK;
+}
+
+template <typename P>
+void bfree(P*& p) {
+  if (p) hipFree(p);
+  p = nullptr;
+}
+
+void free_list(OpList& L) {
+  bfree(L.d_ops);
+  bfree(L.d_tiles);
+  if (L.d_done) hipFree((void*)L.d_done);
+  L.d_done = nullptr;
+  L.cap = 0;
+}
+
+void free_sys(BSys& s) {
+  for (double** p : {&s.H, &s.S, &s.T, &s.Hs64, &s.P64, &s.C64, &s.HW, &s.SW, &s.H1, &s.S1, &s.H2,
+                     &s.S2, &s.partials, &s.trace})
+    bfree(*p);
+  for (float** p : {&s.Hs, &s.S32, &s.P, &s.C, &s.HC, &s.SC, &s.G0, &s.G1, &s.PG, &s.D, &s.HD,
+                    &s.SD})
+    bfree(*p);
+}
+
+bool host_symmetric(const double* A, int64_t n, bool* finite) {
+  *finite = true;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = i; j < n; ++j) {
+      const double a = A[i * n + j], c = A[j * n + i];
+      if (!std::isfinite(a) || !std::isfinite(c)) {
+        *finite = false;
+        return false;
+      }
+      if (!(fabs(a - c) <= 1e-10 * fmax(1.0, fmax(fabs(a), fabs(c))))) return false;
+    }
+  return true;
+}
+
+int alloc_sys_work(omm_batch* b, BSys& s, int max_iter) {
+  const size_t mn = (size_t)s.M * s.N, mm = (size_t)s.M * s.M, nn = (size_t)s.N * s.N;
+  BTRY(balloc(b, &s.Hs64, nn));
+  BTRY(balloc(b, &s.Hs, nn));
+  BTRY(balloc(b, &s.S32, nn));
+  BTRY(balloc(b, &s.C64, mn));
+  for (float** p : {&s.C, &s.HC, &s.SC, &s.G0, &s.G1, &s.PG, &s.D, &s.HD, &s.SD})
+    BTRY(balloc(b, p, mn));
+  for (double** p : {&s.HW, &s.SW, &s.H1, &s.S1, &s.H2, &s.S2}) BTRY(balloc(b, p, mm));
+  BTRY(balloc(b, &s.partials, (size_t)GROUP_BLOCKS * NCOEF));
+  if (s.trace_cap < max_iter + 2) {
+    bfree(s.trace);
+    BTRY(balloc(b, &s.trace, (size_t)max_iter + 2));
+    s.trace_cap = max_iter + 2;
+  }
+  return OMM_OK;
+}
+
+// Shift, preconditioner (FP64 Gauss-Jordan) and FP32 operator copies of one system.
+int setup_sys(omm_batch* b, BSys& s, double eta, double tau) {
+  const int64_t nn = s.N * s.N;
+  BHIP(b, shift_hamiltonian(s.H, s.S, eta, s.Hs64, nn, b->stream));
+  BHIP(b, convert_f64_f32(s.Hs64, s.Hs, nn, b->stream));
+  BHIP(b, convert_f64_f32(s.S, s.S32, nn, b->stream));
+  const int kind = !(tau > 0.0) ? 0 : (isinf(tau) ? 1 : 2);
+  if (kind == 2 && !s.have_T) return bfail(b, OMM_E_ARG, "a finite tau > 0 needs T");
+  if (kind != s.p_kind || (kind == 2 && tau != s.p_tau)) {
+    if (kind > 0) {
+      BTRY(balloc(b, &s.P64, (size_t)nn));
+      BTRY(balloc(b, &s.P, (size_t)nn));
+      if (kind == 1) BHIP(b, copy_f64(s.S, s.P64, nn, b->stream));
+      else BHIP(b, axpby_f64(s.S, s.T, s.P64, 1.0, 1.0 / tau, nn, b->stream));
+      const size_t need = invert_work_doubles(s.N);
+      if (need > b->inv_cap) {
+        bfree(b->inv_work);
+        BTRY(balloc(b, &b->inv_work, need));
+        b->inv_cap = need;
+      }
+      int bad = 0;
+      BHIP(b, invert_in_place(s.P64, s.N, b->inv_work, b->stream, &bad));
+      if (bad) {
+        s.p_kind = -1;
+        return bfail(b, OMM_E_PRECON, "preconditioner inversion hit a zero or non-finite pivot");
+      }
+      BHIP(b, symmetrize(s.P64, s.N, b->stream));
+      BHIP(b, convert_f64_f32(s.P64, s.P, nn, b->stream));
+    }
+    s.p_kind = kind;
+    s.p_tau = tau;
+  }
+  return OMM_OK;
+}
+
+GemmOp gop(int M, int N, int K, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+           int64_t ldc, double alpha = 1.0, const void* X = nullptr, int64_t ldx = 0,
+           double beta = 0.0) {
+  GemmOp op{};
+  op.M = M; op.N = N; op.nseg = 1;
+  op.A[0] = A; op.lda[0] = lda;
+  op.B[0] = B; op.ldb[0] = ldb;
+  op.K[0] = K;
+  op.C = C; op.ldc = ldc;
+  op.X = X; op.ldx = ldx;
+  op.alpha = alpha; op.beta = beta;
+  return op;
+}
+
+// Tile prefix sums for `tile`, uploaded with the op list; grid = min(tiles, 2 per CU).
+int upload_list(omm_batch* b, OpList& L, int tile) {
+  const int n = (int)L.ops.size();
+  if (n == 0) return OMM_OK;
+  if (L.cap < n) {
+    free_list(L);
+    BTRY(balloc(b, &L.d_ops, (size_t)n));
+    BTRY(balloc(b, &L.d_tiles, (size_t)n + 1));
+    if (hipMalloc((void**)&L.d_done, n * sizeof(int*)) != hipSuccess)
+      return bfail(b, OMM_E_ALLOC, "hipMalloc failed");
+    L.cap = n;
+  }
+  std::vector<int> ts(n + 1, 0);
+  const int bm = gemm_tile_rows(tile), bn = gemm_tile_cols(tile);
+  for (int i = 0; i < n; ++i)
+    ts[i + 1] = ts[i] + ((L.ops[i].M + bm - 1) / bm) * ((L.ops[i].N + bn - 1) / bn);
+  L.d.tile = tile;
+  L.d.splitk = 1;
+  L.grid = std::min(ts[n], 512);
+  BHIP(b, hipMemcpyAsync(L.d_ops, L.ops.data(), n * sizeof(GemmOp), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(L.d_tiles, ts.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync((void*)L.d_done, L.done.data(), n * sizeof(int*), hipMemcpyHostToDevice,
+                         b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  return OMM_OK;
+}
+
+int launch_list(omm_batch* b, OpList& L) {
+  if (L.ops.empty()) return OMM_OK;
+  BHIP(b, gemm_grouped_launch(L.d, L.d_ops, L.d_tiles, L.d_done, (int)L.ops.size(), L.grid,
+                              b->stream));
+  return OMM_OK;
+}
+
+// Times the grouped launch with each macro tile once (after a warm-up) and keeps the fastest.
+int tune_list(omm_batch* b, OpList& L) {
+  if (L.ops.empty() || L.tuned) return OMM_OK;
+  hipEvent_t e0, e1;
+  BHIP(b, hipEventCreate(&e0));
+  BHIP(b, hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_t = 0;
+  for (int t = 0; t < gemm_num_tiles(); ++t) {
+    BTRY(upload_list(b, L, t));
+    BTRY(launch_list(b, L));
+    BHIP(b, hipEventRecord(e0, b->stream));
+    BTRY(launch_list(b, L));
+    BHIP(b, hipEventRecord(e1, b->stream));
+    BHIP(b, hipEventSynchronize(e1));
+    float ms = 0.f;
+    BHIP(b, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_t = t;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  BTRY(upload_list(b, L, best_t));
+  L.tuned = true;
+  return OMM_OK;
+}
+
+// Builds the op lists of every CG stage from the current buffers.
+int build_lists(omm_batch* b) {
+  for (OpList* L : {&b->init1, &b->init2, &b->grad[0], &b->grad[1], &b->pg[0], &b->pg[1],
+                    &b->hdsd, &b->proj}) {
+    L->ops.clear();
+    L->done.clear();
+    L->tuned = false;
+  }
+  b->init1.d = GemmDesc{CF32, T_F32, T_F32, T_F32, T_F32, KC, KC, 0, 1};
+  b->init2.d = GemmDesc{CF32, T_F32, T_F32, T_F64, T_F64, KC, KC, 0, 1};
+  for (int p = 0; p < 2; ++p) {
+    b->grad[p].d = GemmDesc{CF32, T_F64, T_F32, T_F32, T_F32, KC, RC, 0, 1};
+    b->pg[p].d = GemmDesc{CF32, T_F32, T_F32, T_F32, T_F32, KC, KC, 0, 1};
+  }
+  b->hdsd.d = GemmDesc{CF32, T_F32, T_F32, T_F32, T_F32, KC, KC, 0, 1};
+  b->proj.d = GemmDesc{CF32, T_F32, T_F32, T_F64, T_F64, KC, KC, 0, 1};
+  for (size_t i = 0; i < b->sys.size(); ++i) {
+    BSys& s = b->sys[i];
+    const int M = (int)s.M, N = (int)s.N;
+    const int* dn = &b->st[i].done;
+    b->init1.ops.push_back(gop(M, N, N, s.C, N, s.Hs, N, s.HC, N));
+    b->init1.ops.push_back(gop(M, N, N, s.C, N, s.S32, N, s.SC, N));
+    b->init2.ops.push_back(gop(M, M, N, s.HC, N, s.C, N, s.HW, M));
+    b->init2.ops.push_back(gop(M, M, N, s.SC, N, s.C, N, s.SW, M));
+    for (int k = 0; k < 2; ++k) b->init1.done.push_back(nullptr), b->init2.done.push_back(nullptr);
+    for (int p = 0; p < 2; ++p) {
+      float* G = p ? s.G1 : s.G0;
+      GemmOp g = gop(M, N, M, s.HW, M, s.SC, N, G, N, -4.0, s.HC, N, 8.0);
+      g.nseg = 2;
+      g.A[1] = s.SW; g.lda[1] = M;
+      g.B[1] = s.HC; g.ldb[1] = N;
+      g.K[1] = M;
+      b->grad[p].ops.push_back(g);
+      b->grad[p].done.push_back(dn);
+      if (s.p_kind > 0) {
+        b->pg[p].ops.push_back(gop(M, N, N, G, N, s.P, N, s.PG, N));
+        b->pg[p].done.push_back(dn);
+      }
+    }
+    b->hdsd.ops.push_back(gop(M, N, N, s.D, N, s.Hs, N, s.HD, N));
+    b->hdsd.ops.push_back(gop(M, N, N, s.D, N, s.S32, N, s.SD, N));
+    for (int k = 0; k < 2; ++k) b->hdsd.done.push_back(dn);
+    b->proj.ops.push_back(gop(M, M, N, s.D, N, s.HC, N, s.H1, M));
+    b->proj.ops.push_back(gop(M, M, N, s.D, N, s.SC, N, s.S1, M));
+    b->proj.ops.push_back(gop(M, M, N, s.D, N, s.HD, N, s.H2, M));
+    b->proj.ops.push_back(gop(M, M, N, s.D, N, s.SD, N, s.S2, M));
+    for (int k = 0; k < 4; ++k) b->proj.done.push_back(dn);
+  }
+  for (OpList* L : {&b->init1, &b->init2, &b->grad[0], &b->grad[1], &b->pg[0], &b->pg[1],
+                    &b->hdsd, &b->proj})
+    BTRY(upload_list(b, *L, 1));
+  return OMM_OK;
+}
+
+// One line search of every live system (k = line-search index: parity of G, first flag).
+int batch_iteration(omm_batch* b, int k) {
+  const int n = (int)b->sys.size();
+  const int p = k & 1;
+  BTRY(launch_list(b, b->grad[p]));
+  BTRY(launch_list(b, b->pg[p]));
+  BHIP(b, group_direction(b->d_sys, n, p, k == 0 ? 1 : 0, b->stream));
+  BTRY(launch_list(b, b->hdsd));
+  BTRY(launch_list(b, b->proj));
+  BHIP(b, group_line_search(b->d_sys, n, b->stream));
+  BHIP(b, group_update(b->d_sys, n, b->stream));
+  return OMM_OK;
+}
+
+void drop_graph(omm_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+int read_states(omm_batch* b) {
+  BHIP(b, hipMemcpyAsync(b->st_host, b->st, b->sys.size() * sizeof(DevState),
+                         hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  return OMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -27,17 +353,20 @@ int omm_batch_create(int nsys, const int64_t* N, const int64_t* M, omm_batch** o
   if (!out) return OMM_E_ARG;
   *out = nullptr;
   if (nsys <= 0 || !N || !M) return OMM_E_ARG;
+  for (int i = 0; i < nsys; ++i)
+    if (N[i] <= 0 || M[i] <= 0 || M[i] > N[i] || N[i] > (1 << 16)) return OMM_E_ARG;
   omm_batch* b = new omm_batch();
+  b->sys.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
-    omm_ctx* c = nullptr;
-    int r = omm_create(N[i], M[i], &c);
-    if (r != OMM_OK) {
-      for (omm_ctx* x : b->sys) omm_destroy(x);
-      delete b;
-      return r;
-    }
-    omm_set_precision(c, OMM_FP32, 0);
-    b->sys.push_back(c);
+    b->sys[i].N = N[i];
+    b->sys[i].M = M[i];
+  }
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc((void**)&b->st, nsys * sizeof(DevState)) != hipSuccess ||
+      hipHostMalloc((void**)&b->st_host, nsys * sizeof(DevState), 0) != hipSuccess ||
+      hipMalloc((void**)&b->d_sys, nsys * sizeof(SysDev)) != hipSuccess) {
+    omm_batch_destroy(b);
+    return OMM_E_HIP;
   }
   b->iters.assign(nsys, 0);
   b->E.assign(nsys, 0.0);
@@ -47,7 +376,17 @@ int omm_batch_create(int nsys, const int64_t* N, const int64_t* M, omm_batch** o
 
 int omm_batch_destroy(omm_batch* b) {
   if (!b) return OMM_E_ARG;
-  for (omm_ctx* c : b->sys) omm_destroy(c);
+  if (b->stream) hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  for (BSys& s : b->sys) free_sys(s);
+  for (OpList* L : {&b->init1, &b->init2, &b->grad[0], &b->grad[1], &b->pg[0], &b->pg[1],
+                    &b->hdsd, &b->proj})
+    free_list(*L);
+  bfree(b->st);
+  bfree(b->d_sys);
+  bfree(b->inv_work);
+  if (b->st_host) hipHostFree(b->st_host);
+  if (b->stream) hipStreamDestroy(b->stream);
   delete b;
   return OMM_OK;
 }
@@ -55,21 +394,129 @@ int omm_batch_destroy(omm_batch* b) {
 int omm_batch_set_HS(omm_batch* b, int i, const double* H, const double* S, const double* T) {
   if (!b) return OMM_E_ARG;
   if (i < 0 || i >= (int)b->sys.size()) return bfail(b, OMM_E_ARG, "system index out of range");
-  int r = omm_set_HS(b->sys[i], H, S, T);
-  if (r != OMM_OK) return bfail(b, r, omm_last_error(b->sys[i]));
+  if (!H || !S) return bfail(b, OMM_E_ARG, "H and S are required");
+  BSys& s = b->sys[i];
+  const int64_t n = s.N;
+  const double* mats[3] = {H, S, T};
+  for (int k = 0; k < 3; ++k) {
+    if (!mats[k]) continue;
+    bool fin = true;
+    if (!host_symmetric(mats[k], n, &fin))
+      return bfail(b, fin ? OMM_E_ASYMMETRIC : OMM_E_NONFINITE,
+                   "system " + std::to_string(i) + ": input not finite/symmetric");
+  }
+  const size_t nn = (size_t)n * n;
+  BTRY(balloc(b, &s.H, nn));
+  BTRY(balloc(b, &s.S, nn));
+  BHIP(b, hipMemcpyAsync(s.H, H, nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(s.S, S, nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, symmetrize(s.H, n, b->stream));
+  BHIP(b, symmetrize(s.S, n, b->stream));
+  s.have_T = T != nullptr;
+  if (T) {
+    BTRY(balloc(b, &s.T, nn));
+    BHIP(b, hipMemcpyAsync(s.T, T, nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, symmetrize(s.T, n, b->stream));
+  }
+  BHIP(b, hipStreamSynchronize(b->stream));
+  s.have_HS = true;
+  s.p_kind = -1;
+  drop_graph(b);
   return OMM_OK;
 }
 
 int omm_batch_minimize(omm_batch* b, const double* const* C0, const double* eta, const double* tau,
                        double tol, int max_iter) {
   if (!b || !eta || !tau) return b ? bfail(b, OMM_E_ARG, "eta and tau are required") : OMM_E_ARG;
+  if (!(tol >= 0.0) || max_iter < 0) return bfail(b, OMM_E_ARG, "need tol >= 0, max_iter >= 0");
+  const int n = (int)b->sys.size();
+  std::vector<SysDev> sd(n);
+  for (int i = 0; i < n; ++i) {
+    BSys& s = b->sys[i];
+    if (!s.have_HS) return bfail(b, OMM_E_STATE, "system " + std::to_string(i) + " has no H/S");
+    if ((!C0 || !C0[i]) && !s.have_C)
+      return bfail(b, OMM_E_STATE, "system " + std::to_string(i) + ": no C0 and no C to resume");
+    BTRY(alloc_sys_work(b, s, max_iter));
+    BTRY(setup_sys(b, s, eta[i], tau[i]));
+    const size_t mn = (size_t)s.M * s.N;
+    if (C0 && C0[i]) {
+      BHIP(b, hipMemcpyAsync(s.C64, C0[i], mn * sizeof(double), hipMemcpyHostToDevice, b->stream));
+      BHIP(b, convert_f64_f32(s.C64, s.C, (int64_t)mn, b->stream));
+    }
+    s.have_C = true;
+    sd[i] = SysDev{s.C, s.HC, s.SC, s.G0, s.G1, s.PG, s.D, s.HD, s.SD, s.HW, s.SW, s.H1, s.S1,
+                   s.H2, s.S2, s.partials, b->st + i, s.trace, (int)s.M, (int)s.N,
+                   s.p_kind > 0 ? 1 : 0};
+    DevState& h = b->st_host[i];
+    h = DevState{};
+    h.tol = tol;
+    h.max_iter = max_iter;
+  }
+  BHIP(b, hipMemcpyAsync(b->d_sys, sd.data(), n * sizeof(SysDev), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(b->st, b->st_host, n * sizeof(DevState), hipMemcpyHostToDevice, b->stream));
+  drop_graph(b);
+  BTRY(build_lists(b));
+
+  // initial products and E_0 of every system
+  BTRY(tune_list(b, b->init1));
+  BTRY(launch_list(b, b->init1));
+  BTRY(tune_list(b, b->init2));
+  BTRY(launch_list(b, b->init2));
+  BHIP(b, group_energy_init(b->d_sys, n, b->stream));
+  BTRY(read_states(b));
+  bool all_done = true;
+  for (int i = 0; i < n; ++i) all_done = all_done && b->st_host[i].done != 0;
+  if (max_iter > 0 && !all_done) {
+    // first line search eagerly (autotunes each grouped product while every system is live)
+    BTRY(tune_list(b, b->grad[0]));
+    BTRY(tune_list(b, b->pg[0]));
+    b->grad[1].d.tile = b->grad[0].d.tile;
+    b->pg[1].d.tile = b->pg[0].d.tile;
+    BTRY(upload_list(b, b->grad[1], b->grad[0].d.tile));
+    BTRY(upload_list(b, b->pg[1], b->pg[0].d.tile));
+    BTRY(launch_list(b, b->grad[0]));
+    BTRY(launch_list(b, b->pg[0]));
+    BHIP(b, group_direction(b->d_sys, n, 0, 1, b->stream));
+    BTRY(tune_list(b, b->hdsd));
+    BTRY(launch_list(b, b->hdsd));
+    BTRY(tune_list(b, b->proj));
+    BTRY(launch_list(b, b->proj));
+    BHIP(b, group_line_search(b->d_sys, n, b->stream));
+    BHIP(b, group_update(b->d_sys, n, b->stream));
+    // line searches 1 and 2 (parities 1, 0) captured once, replayed until all systems stop
+    BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int r1 = batch_iteration(b, 1);
+    int r2 = r1 == OMM_OK ? batch_iteration(b, 2) : r1;
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(b->stream, &g);
+    if (r1 != OMM_OK || r2 != OMM_OK) {
+      if (g) hipGraphDestroy(g);
+      return r1 != OMM_OK ? r1 : r2;
+    }
+    BHIP(b, ec);
+    b->graph = g;
+    BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    const int launches = (max_iter + 1) / 2;
+    for (int l = 0; l < launches; ++l) {
+      BHIP(b, hipGraphLaunch(b->exec, b->stream));
+      if ((l + 1) % 4 == 0 || l + 1 == launches) {
+        BTRY(read_states(b));
+        all_done = true;
+        for (int i = 0; i < n; ++i) all_done = all_done && b->st_host[i].done != 0;
+        if (all_done) break;
+      }
+    }
+  }
+  BTRY(read_states(b));
   int worst = OMM_OK;
-  for (size_t i = 0; i < b->sys.size(); ++i) {
-    int r = omm_minimize(b->sys[i], C0 ? C0[i] : nullptr, eta[i], tau[i], tol, max_iter);
-    if (r < 0) return bfail(b, r, "system " + std::to_string(i) + ": " + omm_last_error(b->sys[i]));
-    if (r > 0) worst = r;
-    omm_stats(b->sys[i], &b->iters[i], nullptr);
-    omm_energy(b->sys[i], &b->E[i]);
+  for (int i = 0; i < n; ++i) {
+    const DevState& h = b->st_host[i];
+    b->iters[i] = h.iter;
+    b->E[i] = h.E;
+    if (h.done < 0)
+      return bfail(b, h.done, "system " + std::to_string(i) + " stopped with error " +
+                                  std::to_string(h.done));
+    if (h.done != 1) worst = OMM_W_MAXITER;
   }
   return worst;
 }
@@ -89,7 +536,13 @@ int omm_batch_iterations(omm_batch* b, int* iters) {
 int omm_batch_get_C(omm_batch* b, int i, double* C) {
   if (!b || !C) return OMM_E_ARG;
   if (i < 0 || i >= (int)b->sys.size()) return bfail(b, OMM_E_ARG, "system index out of range");
-  return omm_get_C(b->sys[i], C);
+  BSys& s = b->sys[i];
+  if (!s.have_C || !s.C) return bfail(b, OMM_E_STATE, "system has no C");
+  const size_t mn = (size_t)s.M * s.N;
+  BHIP(b, convert_f32_f64(s.C, s.C64, (int64_t)mn, b->stream));
+  BHIP(b, hipMemcpyAsync(C, s.C64, mn * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  return OMM_OK;
 }
 
 const char* omm_batch_last_error(const omm_batch* b) {

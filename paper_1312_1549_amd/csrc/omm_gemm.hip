@@ -8,6 +8,7 @@ namespace gemm_detail {
 gemm_fn pick_f64(const GemmDesc& d);
 gemm_fn pick_f32(const GemmDesc& d);
 gemm_fn pick_bf16x3(const GemmDesc& d);
+grouped_fn pick_grouped_f32(const GemmDesc& d);
 
 namespace {
 template <typename TC, typename TX>
@@ -46,6 +47,19 @@ bool gemm_supported(const GemmDesc& d) {
   if (d.compute == CBF16X3) return pick_bf16x3(d) != nullptr;
   return false;
 }
+
+hipError_t gemm_grouped_launch(const GemmDesc& d, const GemmOp* d_ops, const int* d_tile_start,
+                               const int* const* d_done, int nops, int grid, hipStream_t s) {
+  if (d.compute != CF32 || nops < 1 || grid < 1) return hipErrorInvalidValue;
+  grouped_fn fn = pick_grouped_f32(d);
+  if (!fn) return hipErrorInvalidValue;
+  GroupedArgs g{d_ops, d_tile_start, d_done, nops};
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(tile_threads(d.tile)), 0, s, g);
+  return hipGetLastError();
+}
+
+int gemm_tile_rows(int tile) { return tile_bm(tile); }
+int gemm_tile_cols(int tile) { return tile_bn(tile); }
 
 hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int* done, double* ws,
                        size_t ws_bytes, hipStream_t s) {

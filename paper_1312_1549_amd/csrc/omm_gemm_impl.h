@@ -284,12 +284,12 @@ struct AccT<CF64> {
   typedef d4 type;
 };
 
-// WM x WN waves per workgroup, each wave TM x TN blocks of 16 x 16; BK = K tile.
+// One output tile (tm, tn) of op, K split `sp` of `nsplit`. WM x WN waves, each wave TM x TN
+// blocks of 16 x 16; BK = K tile. Split-K partials go to ws[(sp * nops + z) * M * N + ...].
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB, int WM,
-          int WN, int TM, int TN, int BK, int MINW>
-__global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch, const int* done,
-                                                                  int nsplit, double* ws) {
-  if (done && *done) return;
+          int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int sp, int nsplit,
+                                          double* ws, int z, int nops) {
   constexpr int NT = WM * WN * 64;
   constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
   typedef Stager<MODE, TA, LA, BM, BK, NT> SA;
@@ -299,11 +299,6 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch
   constexpr int NBUF = MODE == CBF16X3 ? 2 : 1;  // hi + lo planes
   typedef typename AccT<MODE>::type acc_t;
 
-  const GemmOp& op = batch.op[blockIdx.z];
-  const int tiles_m = (op.M + BM - 1) / BM, tiles_n = (op.N + BN - 1) / BN;
-  int tm, tn;
-  if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
-  const int sp = blockIdx.y;
   const int m0 = tm * BM, n0 = tn * BN;
 
   __shared__ __attribute__((aligned(16))) lds_t As[2][NBUF][BM * RS];
@@ -399,7 +394,6 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch
     }
   }
 
-  const int nops = gridDim.z;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -412,7 +406,7 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch
         if (row < op.M && col < op.N) {
           const double s = (double)acc[i][j][r];
           if (nsplit > 1) {
-            ws[((int64_t)sp * nops + blockIdx.z) * op.M * op.N + (int64_t)row * op.N + col] = s;
+            ws[((int64_t)sp * nops + z) * op.M * op.N + (int64_t)row * op.N + col] = s;
           } else {
             double v = op.alpha * s;
             if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
@@ -422,12 +416,72 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch
       }
 }
 
+// Up to 4 same-shape products (blockIdx.z), XCD-remapped tiles (blockIdx.x), split-K (y).
+template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB, int WM,
+          int WN, int TM, int TN, int BK, int MINW>
+__global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch, const int* done,
+                                                                  int nsplit, double* ws) {
+  if (done && *done) return;
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
+  const GemmOp& op = batch.op[blockIdx.z];
+  const int tiles_m = (op.M + BM - 1) / BM, tiles_n = (op.N + BN - 1) / BN;
+  int tm, tn;
+  if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
+  gemm_tile<MODE, TA, TB, TC, TX, LA, LB, WM, WN, TM, TN, BK>(op, tm, tn, blockIdx.y, nsplit, ws,
+                                                             blockIdx.z, gridDim.z);
+}
+
+// Grouped products of uneven shapes: a persistent grid walks the concatenated tile list of all
+// ops (tile_start = prefix sums); an op whose `done` flag is set is skipped.
+struct GroupedArgs {
+  const GemmOp* ops;
+  const int* tile_start;  // nops + 1 entries
+  const int* const* done; // per op, nullable entries
+  int nops;
+};
+
+template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB, int WM,
+          int WN, int TM, int TN, int BK, int MINW>
+__global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_grouped_kernel(GroupedArgs g) {
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
+  const int total = g.tile_start[g.nops];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = g.nops - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (g.tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int* dn = g.done[lo];
+    if (dn && *dn) continue;
+    const GemmOp op = g.ops[lo];
+    const int tiles_m = (op.M + BM - 1) / BM;
+    const int local = t - g.tile_start[lo];
+    gemm_tile<MODE, TA, TB, TC, TX, LA, LB, WM, WN, TM, TN, BK>(op, local % tiles_m,
+                                                               local / tiles_m, 0, 1, nullptr, 0, 1);
+    __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+typedef void (*grouped_fn)(GroupedArgs);
+
 // Tile shapes (macro tile M x N): 0: 128x128 (4 waves), 1: 64x64 (4 waves), 2: 256x128
 // (8 waves), 3: 128x256 (8 waves).
 constexpr int NTILES = 4;
 inline int tile_bm(int t) { return t == 1 ? 64 : (t == 2 ? 256 : 128); }
 inline int tile_bn(int t) { return t == 1 ? 64 : (t == 3 ? 256 : 128); }
 inline int tile_threads(int t) { return t >= 2 ? 512 : 256; }
+
+template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB>
+grouped_fn pick_grouped_tile(int tile) {
+  constexpr int BK = MODE == CBF16X3 ? 32 : 16;
+  switch (tile) {
+    case 0: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 4, 4, BK, 1>;
+    case 1: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 2, 2, BK, 2>;
+    case 2: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 4, 2, 4, 4, BK, 1>;
+    case 3: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 4, 4, BK, 1>;
+    default: return nullptr;
+  }
+}
 
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB>
 gemm_fn pick_tile(int tile) {

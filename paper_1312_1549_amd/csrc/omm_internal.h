@@ -64,6 +64,13 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
 size_t gemm_splitk_ws_bytes(const GemmOp* ops, int nops, int splitk);
 int gemm_num_tiles();
 bool gemm_supported(const GemmDesc& d);
+int gemm_tile_rows(int tile);
+int gemm_tile_cols(int tile);
+// Grouped FP32 products of uneven shapes in one persistent launch of `grid` workgroups. All
+// arrays are device memory: nops ops, tile prefix sums (nops + 1, computed with the tile shape of
+// d.tile), per-op done flags (entries nullable). No split-K.
+hipError_t gemm_grouped_launch(const GemmDesc& d, const GemmOp* d_ops, const int* d_tile_start,
+                               const int* const* d_done, int nops, int grid, hipStream_t s);
 
 // ---- elementwise / reduction kernels (omm_kernels.hip) ----
 // Number of per-block partial sums each reduction writes is at most RED_BLOCKS.
@@ -108,6 +115,23 @@ hipError_t identity_minus(const double* SW, double* out, int M, double diag, dou
 hipError_t axpby_f64(const double* a, const double* b, double* out, double ca, double cb, int64_t n,
                      hipStream_t s);
 hipError_t scale_f64(double* a, double c, int64_t n, hipStream_t s);
+
+// ---- grouped (batched) stages: one launch over many systems, blockIdx.y = system ----
+struct SysDev {
+  float *C, *HC, *SC, *G0, *G1, *PG, *D, *HD, *SD;  // M x N (FP32)
+  double *HW, *SW, *H1, *S1, *H2, *S2;              // M x M (FP64)
+  double* partials;                                 // GROUP_BLOCKS x NCOEF
+  DevState* st;
+  double* trace;                                    // max_iter + 2 entries
+  int M, N;
+  int precon;                                       // PG holds G P (else PG aliases G)
+};
+constexpr int GROUP_BLOCKS = 64;
+
+hipError_t group_energy_init(const SysDev* d_sys, int nsys, hipStream_t s);
+hipError_t group_direction(const SysDev* d_sys, int nsys, int parity, int first, hipStream_t s);
+hipError_t group_line_search(const SysDev* d_sys, int nsys, hipStream_t s);
+hipError_t group_update(const SysDev* d_sys, int nsys, hipStream_t s);
 
 // ---- preconditioner (omm_precon.hip) ----
 // In-place inverse of an n x n matrix by a blocked Gauss-Jordan sweep. Returns hipSuccess and

@@ -145,11 +145,11 @@ __global__ void k_symmetrize(double* A, int64_t n) {
 }
 
 // ---- energy of (HW, SW): Eq. 8 -----------------------------------------------------------------
-__global__ void k_energy_partials(const double* HW, const double* SW, int M, double* partials) {
+__device__ __forceinline__ void b_energy_partials(const double* HW, const double* SW, int M, double* partials, int bid, int nb) {
   __shared__ double sh[NT / 64];
   const int64_t n = (int64_t)M * M;
   double tr = 0.0, f = 0.0, trs = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+  for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n; i += (int64_t)nb * NT) {
     const int r = (int)(i / M), c = (int)(i % M);
     const double h = HW[i], s = SW[i];
     f += s * h;
@@ -159,13 +159,17 @@ __global__ void k_energy_partials(const double* HW, const double* SW, int M, dou
   double b = block_sum(f, sh);
   double c = block_sum(trs, sh);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x * 3 + 0] = a;
-    partials[blockIdx.x * 3 + 1] = b;
-    partials[blockIdx.x * 3 + 2] = c;
+    partials[bid * 3 + 0] = a;
+    partials[bid * 3 + 1] = b;
+    partials[bid * 3 + 2] = c;
   }
 }
 
-__global__ void k_energy_init_final(const double* partials, int nb, DevState* st, double* trace) {
+__global__ void k_energy_partials(const double* HW, const double* SW, int M, double* partials) {
+  b_energy_partials(HW, SW, M, partials, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void f_energy_init_final(const double* partials, int nb, DevState* st, double* trace) {
   __shared__ double sh[NT / 64];
   const double tr = sum_partials(partials, nb, 3, 0, sh);
   const double f = sum_partials(partials, nb, 3, 1, sh);
@@ -177,14 +181,18 @@ __global__ void k_energy_init_final(const double* partials, int nb, DevState* st
   if (!isfinite(E)) st->done = -5;
 }
 
+__global__ void k_energy_init_final(const double* partials, int nb, DevState* st, double* trace) {
+  f_energy_init_final(partials, nb, st, trace);
+}
+
 // ---- Polak-Ribiere coefficient and direction ----------------------------------------------------
 template <typename T>
-__global__ void k_pr_partials(const T* G, const T* PG, const T* Gp, int64_t n, int first,
-                              double* partials, const DevState* st) {
+__device__ __forceinline__ void b_pr_partials(const T* G, const T* PG, const T* Gp, int64_t n, int first,
+                              double* partials, const DevState* st, int bid, int nb) {
   if (st->done) return;
   __shared__ double sh[NT / 64];
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+  for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n; i += (int64_t)nb * NT) {
     const double pg = (double)PG[i];
     s1 += pg * (double)G[i];
     if (!first) s2 += pg * (double)Gp[i];
@@ -192,12 +200,18 @@ __global__ void k_pr_partials(const T* G, const T* PG, const T* Gp, int64_t n, i
   double a = block_sum(s1, sh);
   double b = block_sum(s2, sh);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x * 2 + 0] = a;
-    partials[blockIdx.x * 2 + 1] = b;
+    partials[bid * 2 + 0] = a;
+    partials[bid * 2 + 1] = b;
   }
 }
 
-__global__ void k_pr_final(const double* partials, int nb, int first, DevState* st) {
+template <typename T>
+__global__ void k_pr_partials(const T* G, const T* PG, const T* Gp, int64_t n, int first,
+                              double* partials, const DevState* st) {
+  b_pr_partials(G, PG, Gp, n, first, partials, st, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void f_pr_final(const double* partials, int nb, int first, DevState* st) {
   if (st->done) return;
   __shared__ double sh[NT / 64];
   const double s1 = sum_partials(partials, nb, 2, 0, sh);
@@ -212,14 +226,23 @@ __global__ void k_pr_final(const double* partials, int nb, int first, DevState* 
   st->pg_g = s1;
 }
 
+__global__ void k_pr_final(const double* partials, int nb, int first, DevState* st) {
+  f_pr_final(partials, nb, first, st);
+}
+
 template <typename T>
-__global__ void k_direction(const T* PG, T* D, int64_t n, int first, const DevState* st) {
+__device__ __forceinline__ void b_direction(const T* PG, T* D, int64_t n, int first, const DevState* st, int bid, int nb) {
   if (st->done) return;
   const double beta = st->beta;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+  for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n; i += (int64_t)nb * NT) {
     const double d = first ? -(double)PG[i] : -(double)PG[i] + beta * (double)D[i];
     D[i] = (T)d;
   }
+}
+
+template <typename T>
+__global__ void k_direction(const T* PG, T* D, int64_t n, int first, const DevState* st) {
+  b_direction(PG, D, n, first, st, blockIdx.x, gridDim.x);
 }
 
 // ---- quartic coefficients (Eq. 13) --------------------------------------------------------------
@@ -229,9 +252,9 @@ __global__ void k_direction(const T* PG, T* D, int64_t n, int first, const DevSt
 //  10 <S'',H'> 11 <S',H''> 12 <S'',H''>
 // With HW, SW, H'', S'' symmetric, Tr{A B} = <A, B> whenever A or B is symmetric; only
 // Tr{S' H'} needs the transposed access.
-__global__ void k_coef_partials(const double* HW, const double* SW, const double* H1,
+__device__ __forceinline__ void b_coef_partials(const double* HW, const double* SW, const double* H1,
                                 const double* S1, const double* H2, const double* S2, int M,
-                                double* partials, const DevState* st) {
+                                double* partials, const DevState* st, int bid, int nb) {
   if (st->done) return;
   __shared__ double t[32][33];
   __shared__ double sh[NT / 64];
@@ -241,7 +264,7 @@ __global__ void k_coef_partials(const double* HW, const double* SW, const double
   const int tb = (M + 31) / 32;
   const int ntiles = tb * tb;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bid; tile < ntiles; tile += nb) {
     const int bi = (tile / tb) * 32, bj = (tile % tb) * 32;
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
@@ -271,8 +294,14 @@ __global__ void k_coef_partials(const double* HW, const double* SW, const double
   }
   for (int k = 0; k < NCOEF; ++k) {
     const double v = block_sum(acc[k], sh);
-    if (threadIdx.x == 0) partials[blockIdx.x * NCOEF + k] = v;
+    if (threadIdx.x == 0) partials[bid * NCOEF + k] = v;
   }
+}
+
+__global__ void k_coef_partials(const double* HW, const double* SW, const double* H1,
+                                const double* S1, const double* H2, const double* S2, int M,
+                                double* partials, const DevState* st) {
+  b_coef_partials(HW, SW, H1, S1, H2, S2, M, partials, st, blockIdx.x, gridDim.x);
 }
 
 // Line minimum of q(x) = sum_k a_k x^k: the first local minimum met going downhill from x = 0
@@ -352,7 +381,7 @@ __device__ int line_minimum(const double* a, double* xout) {
   return found;
 }
 
-__global__ void k_line_final(const double* partials, int nb, DevState* st) {
+__device__ __forceinline__ void f_line_final(const double* partials, int nb, DevState* st) {
   if (st->done) return;
   __shared__ double sh[NT / 64];
   double s[NCOEF];
@@ -372,23 +401,33 @@ __global__ void k_line_final(const double* partials, int nb, DevState* st) {
   st->x = x;
 }
 
+__global__ void k_line_final(const double* partials, int nb, DevState* st) {
+  f_line_final(partials, nb, st);
+}
+
 // ---- updates (Eq. 16 and the footnote of Sec. 2.3) ----------------------------------------------
 template <typename T>
-__global__ void k_update_mn(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
-                            const DevState* st) {
+__device__ __forceinline__ void b_update_mn(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
+                            const DevState* st, int bid, int nb) {
   if (st->done) return;
   const double x = st->x;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+  for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n; i += (int64_t)nb * NT) {
     C[i] = (T)((double)C[i] + x * (double)D[i]);
     HC[i] = (T)((double)HC[i] + x * (double)HD[i]);
     SC[i] = (T)((double)SC[i] + x * (double)SD[i]);
   }
 }
 
-// HW += x (H' + H'^T) + x^2 H'', SW likewise; partial sums of Tr HW, <SW, HW>, Tr SW.
-__global__ void k_update_mm(double* HW, double* SW, const double* H1, const double* S1,
-                            const double* H2, const double* S2, int M, double* partials,
+template <typename T>
+__global__ void k_update_mn(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
                             const DevState* st) {
+  b_update_mn(C, D, HC, HD, SC, SD, n, st, blockIdx.x, gridDim.x);
+}
+
+// HW += x (H' + H'^T) + x^2 H'', SW likewise; partial sums of Tr HW, <SW, HW>, Tr SW.
+__device__ __forceinline__ void b_update_mm(double* HW, double* SW, const double* H1, const double* S1,
+                            const double* H2, const double* S2, int M, double* partials,
+                            const DevState* st, int bid, int nb) {
   if (st->done) return;
   __shared__ double th[32][33], ts[32][33];
   __shared__ double sh[NT / 64];
@@ -397,7 +436,7 @@ __global__ void k_update_mm(double* HW, double* SW, const double* H1, const doub
   const int tb = (M + 31) / 32;
   const int ntiles = tb * tb;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bid; tile < ntiles; tile += nb) {
     const int bi = (tile / tb) * 32, bj = (tile % tb) * 32;
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
@@ -424,13 +463,19 @@ __global__ void k_update_mm(double* HW, double* SW, const double* H1, const doub
   const double b = block_sum(f, sh);
   const double c = block_sum(trs, sh);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x * 3 + 0] = a;
-    partials[blockIdx.x * 3 + 1] = b;
-    partials[blockIdx.x * 3 + 2] = c;
+    partials[bid * 3 + 0] = a;
+    partials[bid * 3 + 1] = b;
+    partials[bid * 3 + 2] = c;
   }
 }
 
-__global__ void k_update_final(const double* partials, int nb, int M, DevState* st,
+__global__ void k_update_mm(double* HW, double* SW, const double* H1, const double* S1,
+                            const double* H2, const double* S2, int M, double* partials,
+                            const DevState* st) {
+  b_update_mm(HW, SW, H1, S1, H2, S2, M, partials, st, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void f_update_final(const double* partials, int nb, int M, DevState* st,
                                double* trace) {
   if (st->done) return;
   __shared__ double sh[NT / 64];
@@ -452,6 +497,11 @@ __global__ void k_update_final(const double* partials, int nb, int M, DevState* 
   if (st->iter >= st->max_iter) st->done = 2;
 }
 
+__global__ void k_update_final(const double* partials, int nb, int M, DevState* st,
+                               double* trace) {
+  f_update_final(partials, nb, M, st, trace);
+}
+
 __global__ void k_identity_minus(const double* SW, double* out, int M, double diag, double scale) {
   const int64_t n = (int64_t)M * M;
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
@@ -469,6 +519,54 @@ __global__ void k_axpby(const double* a, const double* b, double* out, double ca
 __global__ void k_scale(double* a, double c, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
     a[i] *= c;
+}
+
+// ---- grouped kernels (blockIdx.y = system) -----------------------------------------------------
+__global__ void g_energy_partials(const SysDev* sys) {
+  const SysDev& d = sys[blockIdx.y];
+  b_energy_partials(d.HW, d.SW, d.M, d.partials, blockIdx.x, gridDim.x);
+}
+__global__ void g_energy_init_final(const SysDev* sys) {
+  const SysDev& d = sys[blockIdx.y];
+  f_energy_init_final(d.partials, GROUP_BLOCKS, d.st, d.trace);
+}
+__global__ void g_pr_partials(const SysDev* sys, int parity, int first) {
+  const SysDev& d = sys[blockIdx.y];
+  const float* G = parity ? d.G1 : d.G0;
+  const float* Gp = parity ? d.G0 : d.G1;
+  b_pr_partials<float>(G, d.precon ? d.PG : G, Gp, (int64_t)d.M * d.N, first, d.partials, d.st,
+                       blockIdx.x, gridDim.x);
+}
+__global__ void g_pr_final(const SysDev* sys, int first) {
+  const SysDev& d = sys[blockIdx.y];
+  f_pr_final(d.partials, GROUP_BLOCKS, first, d.st);
+}
+__global__ void g_direction(const SysDev* sys, int parity, int first) {
+  const SysDev& d = sys[blockIdx.y];
+  const float* G = parity ? d.G1 : d.G0;
+  b_direction<float>(d.precon ? d.PG : G, d.D, (int64_t)d.M * d.N, first, d.st, blockIdx.x,
+                     gridDim.x);
+}
+__global__ void g_coef_partials(const SysDev* sys) {
+  const SysDev& d = sys[blockIdx.y];
+  b_coef_partials(d.HW, d.SW, d.H1, d.S1, d.H2, d.S2, d.M, d.partials, d.st, blockIdx.x, gridDim.x);
+}
+__global__ void g_line_final(const SysDev* sys) {
+  const SysDev& d = sys[blockIdx.y];
+  f_line_final(d.partials, GROUP_BLOCKS, d.st);
+}
+__global__ void g_update_mn(const SysDev* sys) {
+  const SysDev& d = sys[blockIdx.y];
+  b_update_mn<float>(d.C, d.D, d.HC, d.HD, d.SC, d.SD, (int64_t)d.M * d.N, d.st, blockIdx.x,
+                     gridDim.x);
+}
+__global__ void g_update_mm(const SysDev* sys) {
+  const SysDev& d = sys[blockIdx.y];
+  b_update_mm(d.HW, d.SW, d.H1, d.S1, d.H2, d.S2, d.M, d.partials, d.st, blockIdx.x, gridDim.x);
+}
+__global__ void g_update_final(const SysDev* sys) {
+  const SysDev& d = sys[blockIdx.y];
+  f_update_final(d.partials, GROUP_BLOCKS, d.M, d.st, d.trace);
 }
 
 int tile_blocks(int M) {
@@ -579,6 +677,32 @@ hipError_t update_subspace(double* HW, double* SW, const double* H1, const doubl
   hipLaunchKernelGGL(k_update_mm, dim3(nb), dim3(NT), 0, s, HW, SW, H1, S1, H2, S2, M, partials,
                      st);
   hipLaunchKernelGGL(k_update_final, dim3(1), dim3(NT), 0, s, partials, nb, M, st, trace);
+  return hipGetLastError();
+}
+
+hipError_t group_energy_init(const SysDev* d_sys, int nsys, hipStream_t s) {
+  hipLaunchKernelGGL(g_energy_partials, dim3(GROUP_BLOCKS, nsys), dim3(NT), 0, s, d_sys);
+  hipLaunchKernelGGL(g_energy_init_final, dim3(1, nsys), dim3(NT), 0, s, d_sys);
+  return hipGetLastError();
+}
+
+hipError_t group_direction(const SysDev* d_sys, int nsys, int parity, int first, hipStream_t s) {
+  hipLaunchKernelGGL(g_pr_partials, dim3(GROUP_BLOCKS, nsys), dim3(NT), 0, s, d_sys, parity, first);
+  hipLaunchKernelGGL(g_pr_final, dim3(1, nsys), dim3(NT), 0, s, d_sys, first);
+  hipLaunchKernelGGL(g_direction, dim3(4 * GROUP_BLOCKS, nsys), dim3(NT), 0, s, d_sys, parity, first);
+  return hipGetLastError();
+}
+
+hipError_t group_line_search(const SysDev* d_sys, int nsys, hipStream_t s) {
+  hipLaunchKernelGGL(g_coef_partials, dim3(GROUP_BLOCKS, nsys), dim3(NT), 0, s, d_sys);
+  hipLaunchKernelGGL(g_line_final, dim3(1, nsys), dim3(NT), 0, s, d_sys);
+  return hipGetLastError();
+}
+
+hipError_t group_update(const SysDev* d_sys, int nsys, hipStream_t s) {
+  hipLaunchKernelGGL(g_update_mn, dim3(4 * GROUP_BLOCKS, nsys), dim3(NT), 0, s, d_sys);
+  hipLaunchKernelGGL(g_update_mm, dim3(GROUP_BLOCKS, nsys), dim3(NT), 0, s, d_sys);
+  hipLaunchKernelGGL(g_update_final, dim3(1, nsys), dim3(NT), 0, s, d_sys);
   return hipGetLastError();
 }
 

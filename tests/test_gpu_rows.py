@@ -129,6 +129,33 @@ def test_batched_systems_match_closed_forms(torch):
     assert np.all(it_warm < it_cold)
 
 
+def test_grouped_batch_matches_single_system_runs(torch):
+    """The grouped launches (persistent GEMMs over all systems' tiles, hipGraph replays) give
+    the energies of independent single-system FP32 runs, and a second call (a new graph)
+    reproduces the first."""
+    from paper_1312_1549_amd import OMM, OMMBatch
+
+    systems = batched_systems(count=6, first_seed=120)
+    _say("grouped batch vs single " + ",".join(str(x.N) for x in systems))
+    b = OMMBatch([x.N for x in systems], [x.M for x in systems])
+    C0s = [start_coefficients(x.S, x.M, 2000 + i) for i, x in enumerate(systems)]
+    for i, x in enumerate(systems):
+        b.set_HS(i, x.H, x.S, x.T)
+    b.minimize(C0s, [x.eta for x in systems], [x.tau for x in systems], 1e-11, 4000)
+    E1, it1 = b.energies(), b.iterations()
+    b.minimize(C0s, [x.eta for x in systems], [x.tau for x in systems], 1e-11, 4000)
+    E2 = b.energies()
+    assert np.array_equal(E1, E2)
+    for i, x in enumerate(systems):
+        single = OMM(x.N, x.M, precision="fp32", refine=False)
+        single.set_HS(x.H, x.S, x.T)
+        single.minimize(C0s[i], eta=x.eta, tau=x.tau, tol=1e-11, max_iter=4000)
+        assert abs(single.energy() - E1[i]) <= 1e-6 * abs(E1[i])
+        w = brute.generalized_eigh_lapack(x.H, x.S, x.M + 1)[0]
+        ref = brute.closed_form_energy(w, x.M, x.eta)
+        assert abs(E1[i] - ref) <= 1e-5 * abs(ref)
+
+
 def test_full_size_first_line_searches_match_oracle(torch):
     """N=13000, M=2000 in the benchmark's launch configuration: the first line search and the
     state it leaves (C, SW) against the oracle; SW against C S C^T (any-size property)."""
