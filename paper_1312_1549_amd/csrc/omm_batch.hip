@@ -213,7 +213,7 @@ int upload_list(omm_batch* b, OpList& L, int tile) {
     L.cap = n;
   }
   std::vector<int> ts(n + 1, 0);
-  const int bm = gemm_tile_rows(tile), bn = gemm_tile_cols(tile);
+  const int bm = gemm_tile_rows(tile, L.d.compute), bn = gemm_tile_cols(tile, L.d.compute);
   for (int i = 0; i < n; ++i)
     ts[i + 1] = ts[i] + ((L.ops[i].M + bm - 1) / bm) * ((L.ops[i].N + bn - 1) / bn);
   L.d.tile = tile;

@@ -273,7 +273,7 @@ int autotune(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, int K, std::pair<int
     dt.tile = t;
     dt.splitk = 1;
     if (!gemm_supported(dt)) continue;
-    const int bm = t == 1 ? 64 : (t == 2 ? 256 : 128), bn = t == 1 ? 64 : (t == 3 ? 256 : 128);
+    const int bm = gemm_tile_rows(t, d.compute), bn = gemm_tile_cols(t, d.compute);
     const long tiles = (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
     if (tiles >= 32 || t == 1) cands.push_back({t, 1});
     for (int sk : {2, 4, 8, 16})

@@ -54,12 +54,12 @@ hipError_t gemm_grouped_launch(const GemmDesc& d, const GemmOp* d_ops, const int
   grouped_fn fn = pick_grouped_f32(d);
   if (!fn) return hipErrorInvalidValue;
   GroupedArgs g{d_ops, d_tile_start, d_done, nops};
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(tile_threads(d.tile)), 0, s, g);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(tile_threads(d.tile, d.compute)), 0, s, g);
   return hipGetLastError();
 }
 
-int gemm_tile_rows(int tile) { return tile_bm(tile); }
-int gemm_tile_cols(int tile) { return tile_bn(tile); }
+int gemm_tile_rows(int tile, int mode) { return tile_bm(tile, mode); }
+int gemm_tile_cols(int tile, int mode) { return tile_bn(tile, mode); }
 
 hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int* done, double* ws,
                        size_t ws_bytes, hipStream_t s) {
@@ -78,14 +78,14 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
   else if (d.compute == CF32) fn = pick_f32(d);
   else if (d.compute == CBF16X3) fn = pick_bf16x3(d);
   if (!fn) return hipErrorInvalidValue;
-  const int bm = tile_bm(d.tile), bn = tile_bn(d.tile);
+  const int bm = tile_bm(d.tile, d.compute), bn = tile_bn(d.tile, d.compute);
   const int tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
   const int per = (tiles + 7) / 8;
   const int splitk = d.splitk > 1 ? d.splitk : 1;
   if (splitk > 1 && (!ws || ws_bytes < gemm_splitk_ws_bytes(ops, nops, splitk)))
     return hipErrorInvalidValue;
   dim3 grid(8 * per, splitk, nops);
-  hipLaunchKernelGGL(fn, grid, dim3(tile_threads(d.tile)), 0, s, b, done, splitk, ws);
+  hipLaunchKernelGGL(fn, grid, dim3(tile_threads(d.tile, d.compute)), 0, s, b, done, splitk, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splitk == 1) return e;
   const int64_t mn = (int64_t)M * N;

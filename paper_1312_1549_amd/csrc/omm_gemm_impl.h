@@ -112,7 +112,16 @@ struct ModeTraits<CBF16X3> {
 // Global -> register staging of one operand tile (R rows x BK), `NV` vectors of VEC per thread.
 // KC: vector = VEC consecutive k of one row. RC: vector = VEC consecutive rows of one k.
 // TS = unsigned short means pre-split bf16 planes (hi at X, lo at Xlo), copied without conversion.
-template <int MODE, typename TS, int LAYOUT, int R, int BK, int NT>
+// LDS element offset of (row r, k). Padded rows, or (SWZ, BF16x3 with BK = 32) unpadded 64-byte
+// rows whose four 16-byte chunks are rotated by r/4, which keeps the 16 rows read by one
+// quarter-wave on 16 distinct 16-byte bank groups.
+template <bool SWZ, int RS>
+__device__ __forceinline__ int lds_off(int r, int k) {
+  if constexpr (SWZ) return r * RS + ((((k >> 3) + (r >> 2)) & 3) << 3) + (k & 7);
+  else return r * RS + k;
+}
+
+template <int MODE, typename TS, int LAYOUT, int R, int BK, int NT, bool SWZ = false>
 struct Stager {
   static constexpr int VEC = ModeTraits<MODE>::VEC;
   static constexpr int NV = R * BK / VEC / NT;
@@ -120,7 +129,8 @@ struct Stager {
   static constexpr bool PL = std::is_same<TS, unsigned short>::value;
   static_assert(!PL || MODE == CBF16X3, "bf16 planes feed the BF16x3 mode only");
   typedef typename ModeTraits<MODE>::lds_t lds_t;
-  static constexpr int RS = BK + ModeTraits<MODE>::PAD;  // LDS row stride (elements)
+  static_assert(!SWZ || (MODE == CBF16X3 && BK == 32), "swizzle: BF16x3 with BK = 32 only");
+  static constexpr int RS = SWZ ? BK : BK + ModeTraits<MODE>::PAD;  // LDS row stride (elements)
   float rf[(MODE == CF64 || PL) ? 1 : NV * VEC];
   double rd[MODE == CF64 ? NV * VEC : 1];
   u16x8 ph[PL ? NV : 1], pq[PL ? NV : 1];
@@ -221,13 +231,13 @@ struct Stager {
       coords(tid, v, r, k);
       if constexpr (PL) {
         if (LAYOUT == KC) {
-          *reinterpret_cast<u16x8*>(s0 + r * RS + k) = ph[v];
-          *reinterpret_cast<u16x8*>(s1 + r * RS + k) = pq[v];
+          *reinterpret_cast<u16x8*>(s0 + lds_off<SWZ, RS>(r, k)) = ph[v];
+          *reinterpret_cast<u16x8*>(s1 + lds_off<SWZ, RS>(r, k)) = pq[v];
         } else {
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            s0[(r + u) * RS + k] = ph[v][u];
-            s1[(r + u) * RS + k] = pq[v][u];
+            s0[lds_off<SWZ, RS>(r + u, k)] = ph[v][u];
+            s1[lds_off<SWZ, RS>(r + u, k)] = pq[v][u];
           }
         }
       } else if constexpr (MODE == CBF16X3) {
@@ -240,15 +250,15 @@ struct Stager {
             h[u] = hb;
             l[u] = bf16_rne(x - bf16_val(hb));
           }
-          *reinterpret_cast<u16x8*>(s0 + r * RS + k) = h;
-          *reinterpret_cast<u16x8*>(s1 + r * RS + k) = l;
+          *reinterpret_cast<u16x8*>(s0 + lds_off<SWZ, RS>(r, k)) = h;
+          *reinterpret_cast<u16x8*>(s1 + lds_off<SWZ, RS>(r, k)) = l;
         } else {
 #pragma unroll
           for (int u = 0; u < VEC; ++u) {
             const float x = rf[v * VEC + u];
             const unsigned short hb = bf16_rne(x);
-            s0[(r + u) * RS + k] = hb;
-            s1[(r + u) * RS + k] = bf16_rne(x - bf16_val(hb));
+            s0[lds_off<SWZ, RS>(r + u, k)] = hb;
+            s1[lds_off<SWZ, RS>(r + u, k)] = bf16_rne(x - bf16_val(hb));
           }
         }
       } else if constexpr (MODE == CF64) {
@@ -287,13 +297,13 @@ struct AccT<CF64> {
 // One output tile (tm, tn) of op, K split `sp` of `nsplit`. WM x WN waves, each wave TM x TN
 // blocks of 16 x 16; BK = K tile. Split-K partials go to ws[(sp * nops + z) * M * N + ...].
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB, int WM,
-          int WN, int TM, int TN, int BK>
+          int WN, int TM, int TN, int BK, bool SWZ = false>
 __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int sp, int nsplit,
                                           double* ws, int z, int nops) {
   constexpr int NT = WM * WN * 64;
   constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
-  typedef Stager<MODE, TA, LA, BM, BK, NT> SA;
-  typedef Stager<MODE, TB, LB, BN, BK, NT> SB;
+  typedef Stager<MODE, TA, LA, BM, BK, NT, SWZ> SA;
+  typedef Stager<MODE, TB, LB, BN, BK, NT, SWZ> SB;
   typedef typename ModeTraits<MODE>::lds_t lds_t;
   constexpr int RS = SA::RS;
   constexpr int NBUF = MODE == CBF16X3 ? 2 : 1;  // hi + lo planes
@@ -350,23 +360,48 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
         const int kof = 8 * (lane >> 4);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 32) {
-          bf8 ah[TM], al[TM];
+          auto frag = [&](const lds_t* base, int r) {
+            return __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(
+                                               base + lds_off<SWZ, RS>(r, kk + kof)));
+          };
+          if constexpr (TM > TN) {
+            // all B fragments live, one A pair at a time (fewer registers for tall wave tiles)
+            bf8 bh[TN], bl[TN];
 #pragma unroll
-          for (int i = 0; i < TM; ++i) {
-            const int r = wm * TM * 16 + i * 16 + (lane & 15);
-            ah[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(a0 + r * RS + kk + kof));
-            al[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(a1 + r * RS + kk + kof));
-          }
-#pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            const int r = wn * TN * 16 + j * 16 + (lane & 15);
-            const bf8 bh = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(b0 + r * RS + kk + kof));
-            const bf8 bl = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(b1 + r * RS + kk + kof));
+            for (int j = 0; j < TN; ++j) {
+              const int r = wn * TN * 16 + j * 16 + (lane & 15);
+              bh[j] = frag(b0, r);
+              bl[j] = frag(b1, r);
+            }
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+              const int r = wm * TM * 16 + i * 16 + (lane & 15);
+              const bf8 ah = frag(a0, r), al = frag(a1, r);
+#pragma unroll
+              for (int j = 0; j < TN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+              }
+            }
+          } else {
+            bf8 ah[TM], al[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+              const int r = wm * TM * 16 + i * 16 + (lane & 15);
+              ah[i] = frag(a0, r);
+              al[i] = frag(a1, r);
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              const int r = wn * TN * 16 + j * 16 + (lane & 15);
+              const bf8 bh = frag(b0, r), bl = frag(b1, r);
+#pragma unroll
+              for (int i = 0; i < TM; ++i) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+              }
             }
           }
         }
@@ -418,7 +453,7 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
 
 // Up to 4 same-shape products (blockIdx.z), XCD-remapped tiles (blockIdx.x), split-K (y).
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB, int WM,
-          int WN, int TM, int TN, int BK, int MINW>
+          int WN, int TM, int TN, int BK, int MINW, bool SWZ = false>
 __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch, const int* done,
                                                                   int nsplit, double* ws) {
   if (done && *done) return;
@@ -427,8 +462,8 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch
   const int tiles_m = (op.M + BM - 1) / BM, tiles_n = (op.N + BN - 1) / BN;
   int tm, tn;
   if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
-  gemm_tile<MODE, TA, TB, TC, TX, LA, LB, WM, WN, TM, TN, BK>(op, tm, tn, blockIdx.y, nsplit, ws,
-                                                             blockIdx.z, gridDim.z);
+  gemm_tile<MODE, TA, TB, TC, TX, LA, LB, WM, WN, TM, TN, BK, SWZ>(op, tm, tn, blockIdx.y, nsplit,
+                                                                  ws, blockIdx.z, gridDim.z);
 }
 
 // Grouped products of uneven shapes: a persistent grid walks the concatenated tile list of all
@@ -441,7 +476,7 @@ struct GroupedArgs {
 };
 
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB, int WM,
-          int WN, int TM, int TN, int BK, int MINW>
+          int WN, int TM, int TN, int BK, int MINW, bool SWZ = false>
 __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_grouped_kernel(GroupedArgs g) {
   constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
   const int total = g.tile_start[g.nops];
@@ -456,20 +491,27 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_grouped_kernel(Grouped
     const GemmOp op = g.ops[lo];
     const int tiles_m = (op.M + BM - 1) / BM;
     const int local = t - g.tile_start[lo];
-    gemm_tile<MODE, TA, TB, TC, TX, LA, LB, WM, WN, TM, TN, BK>(op, local % tiles_m,
-                                                               local / tiles_m, 0, 1, nullptr, 0, 1);
+    gemm_tile<MODE, TA, TB, TC, TX, LA, LB, WM, WN, TM, TN, BK, SWZ>(
+        op, local % tiles_m, local / tiles_m, 0, 1, nullptr, 0, 1);
     __syncthreads();  // LDS is reused by the next tile
   }
 }
 
 typedef void (*grouped_fn)(GroupedArgs);
 
-// Tile shapes (macro tile M x N): 0: 128x128 (4 waves), 1: 64x64 (4 waves), 2: 256x128
-// (8 waves), 3: 128x256 (8 waves).
-constexpr int NTILES = 4;
-inline int tile_bm(int t) { return t == 1 ? 64 : (t == 2 ? 256 : 128); }
-inline int tile_bn(int t) { return t == 1 ? 64 : (t == 3 ? 256 : 128); }
-inline int tile_threads(int t) { return t >= 2 ? 512 : 256; }
+// Tile shapes (macro tile M x N): 0: 128x128 (4 waves), 1: 64x64 (4 waves, 2 workgroups per
+// CU), 2: 256x128 (8 waves), 3: 128x256 (8 waves), 4: BF16x3: 256x256 (8 waves of 128x64,
+// swizzled unpadded LDS); FP64/FP32: 128x128 with 2 workgroups per CU.
+constexpr int NTILES = 5;
+inline int tile_bm(int t, int mode) {
+  return t == 1 ? 64 : (t == 2 || (t == 4 && mode == CBF16X3) ? 256 : 128);
+}
+inline int tile_bn(int t, int mode) {
+  return t == 1 ? 64 : (t == 3 || (t == 4 && mode == CBF16X3) ? 256 : 128);
+}
+inline int tile_threads(int t, int mode) {
+  return (t == 2 || t == 3 || (t == 4 && mode == CBF16X3)) ? 512 : 256;
+}
 
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB>
 grouped_fn pick_grouped_tile(int tile) {
@@ -479,6 +521,11 @@ grouped_fn pick_grouped_tile(int tile) {
     case 1: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 2, 2, BK, 2>;
     case 2: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 4, 2, 4, 4, BK, 1>;
     case 3: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 4, 4, BK, 1>;
+    case 4:
+      if constexpr (MODE == CBF16X3)
+        return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 8, 4, BK, 1, true>;
+      else
+        return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 4, 4, BK, 2>;
     default: return nullptr;
   }
 }
@@ -491,6 +538,11 @@ gemm_fn pick_tile(int tile) {
     case 1: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 2, 2, BK, 2>;
     case 2: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 4, 2, 4, 4, BK, 1>;
     case 3: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 4, 4, BK, 1>;
+    case 4:
+      if constexpr (MODE == CBF16X3)
+        return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 8, 4, BK, 1, true>;
+      else
+        return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 4, 4, BK, 2>;
     default: return nullptr;
   }
 }

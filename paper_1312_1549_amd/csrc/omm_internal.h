@@ -53,7 +53,7 @@ struct GemmDesc {
   int compute;         // Compute
   int ta, tb, tc, tx;  // ElemType of A, B, C, X
   int la, lb;          // Layout of A, B
-  int tile;            // macro tile (M x N): 0: 128x128, 1: 64x64, 2: 256x128, 3: 128x256
+  int tile;            // macro tile, see gemm_tile_rows / gemm_tile_cols (0..4)
   int splitk;          // >1: K split across workgroups, partials reduced in FP64 (needs ws)
 };
 
@@ -64,8 +64,8 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
 size_t gemm_splitk_ws_bytes(const GemmOp* ops, int nops, int splitk);
 int gemm_num_tiles();
 bool gemm_supported(const GemmDesc& d);
-int gemm_tile_rows(int tile);
-int gemm_tile_cols(int tile);
+int gemm_tile_rows(int tile, int mode);
+int gemm_tile_cols(int tile, int mode);
 // Grouped FP32 products of uneven shapes in one persistent launch of `grid` workgroups. All
 // arrays are device memory: nops ops, tile prefix sums (nops + 1, computed with the tile shape of
 // d.tile), per-op done flags (entries nullable). No split-K.
