@@ -249,7 +249,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison rate")
     ap.add_argument("--max-iter", type=int, default=4000)
-    ap.add_argument("--resync", type=int, default=20)
+    ap.add_argument("--resync", type=int, default=40)
     ap.add_argument("--cpu-iters", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

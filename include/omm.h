@@ -74,7 +74,7 @@ int omm_set_precision(omm_ctx *ctx, int mode, int fp64_refine);
 /* Stopping threshold of the FP32 phase of OMM_FP32 + refinement (default 1e-9). */
 int omm_set_mixed_tol(omm_ctx *ctx, double tol);
 
-/* Line searches between FP64 resynchronizations of OMM_BF16X3 + refinement (default 20). */
+/* Line searches between FP64 resynchronizations of OMM_BF16X3 + refinement (default 40). */
 int omm_set_resync(omm_ctx *ctx, int every);
 
 /* Use `hip_stream` (a hipStream_t) for all work; NULL restores the context's own stream. */

@@ -74,6 +74,7 @@ struct omm_ctx {
   Work<float> w32;
   // BF16x3 operand planes: operators (set up once) and per-iteration operands
   Plane Hs_p, S_p, P_p, C_p, HC_p, SC_p, G_p, D_p, HD_p, SD_p, HW_p, SW_p;
+  Plane HCt_p, SCt_p;  // planes of HC^T, SC^T (N x M): k-contiguous B of the gradient
   bool hsp_valid = false, sp_valid = false, pp_valid = false;
   double *HW = nullptr, *SW = nullptr, *H1 = nullptr, *S1 = nullptr, *H2 = nullptr, *S2 = nullptr;
   double *partials = nullptr, *ws = nullptr;
@@ -92,7 +93,7 @@ struct omm_ctx {
   bool phase_active = false;
   int phase_prec = OMM_FP64;  // precision of the active phase
   bool phase_mixed64 = false; // active phase: BF16x3 products on an FP64 state (with resyncs)
-  int resync_every = 20;      // line searches between FP64 resynchronizations
+  int resync_every = 40;      // line searches between FP64 resynchronizations
   int since_resync = 0;
   double resync_E = 0.0;      // FP64 energy at the last resynchronization
   std::vector<int> ck_iter;   // FP64-exact energies of the mixed scheme: (line search, E)
@@ -509,7 +510,8 @@ Opnd dn(const T* p) { return {p, nullptr}; }
 // Planes for the per-iteration BF16x3 operands (M x N and M x M).
 int alloc_iter_planes(omm_ctx* c) {
   const size_t mn = (size_t)c->M * c->N, mm = (size_t)c->M * c->M;
-  for (Plane* p : {&c->C_p, &c->HC_p, &c->SC_p, &c->G_p, &c->D_p, &c->HD_p, &c->SD_p})
+  for (Plane* p : {&c->C_p, &c->HC_p, &c->SC_p, &c->G_p, &c->D_p, &c->HD_p, &c->SD_p, &c->HCt_p,
+                   &c->SCt_p})
     TRY(alloc_plane(c, *p, mn));
   TRY(alloc_plane(c, c->HW_p, mm));
   TRY(alloc_plane(c, c->SW_p, mm));
@@ -519,6 +521,18 @@ int alloc_iter_planes(omm_ctx* c) {
 template <typename T>
 int split(omm_ctx* c, const T* src, Plane& p, int64_t n, bool check_done = true) {
   HIPCHK(c, split_bf16(src, p.hi, p.lo, n, check_done ? c->st : nullptr, c->stream));
+  return OMM_OK;
+}
+
+// Planes of HC, SC and of their transposes (after every change of HC, SC).
+template <typename T>
+int split_state(omm_ctx* c, const T* HC, const T* SC, bool check_done = true) {
+  const int M = (int)c->M, N = (int)c->N;
+  const DevState* st = check_done ? c->st : nullptr;
+  TRY(split(c, HC, c->HC_p, (int64_t)M * N, check_done));
+  TRY(split(c, SC, c->SC_p, (int64_t)M * N, check_done));
+  HIPCHK(c, split_bf16_t(HC, c->HCt_p.hi, c->HCt_p.lo, M, N, st, c->stream));
+  HIPCHK(c, split_bf16_t(SC, c->SCt_p.hi, c->SCt_p.lo, M, N, st, c->stream));
   return OMM_OK;
 }
 
@@ -540,10 +554,7 @@ int initial_products(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* 
   GemmOp ops[2] = {make_op2(M, N, N, Cop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HC, N),
                    make_op2(M, N, N, Cop, N, bf ? pl(c->S_p) : dn(S), N, w.SC, N)};
   TRY(gemm(c, d, ops, 2, nullptr));
-  if (bf) {
-    TRY(split(c, w.HC, c->HC_p, mn, false));
-    TRY(split(c, w.SC, c->SC_p, mn, false));
-  }
+  if (bf) TRY(split_state(c, w.HC, w.SC, false));
   GemmDesc d2{compute, et, et, T_F64, T_F64, KC, KC, 0, 1};
   GemmOp ops2[2] = {make_op2(M, M, N, bf ? pl(c->HC_p) : dn(w.HC), N, Cop, N, c->HW, M),
                     make_op2(M, M, N, bf ? pl(c->SC_p) : dn(w.SC), N, Cop, N, c->SW, M)};
@@ -601,13 +612,14 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
       TRY(split(c, c->HW, c->HW_p, (int64_t)M * M));
       TRY(split(c, c->SW, c->SW_p, (int64_t)M * M));
     }
-    GemmDesc d{compute, bf ? T_BF16P : T_F64, ot, et, et, KC, RC, 0, 1};
-    GemmOp op = make_op2(M, N, M, bf ? pl(c->HW_p) : dn(c->HW), M, bf ? pl(c->SC_p) : dn(w.SC), N,
-                         G, N, -4.0, w.HC, N, 8.0);
-    const Opnd a2 = bf ? pl(c->SW_p) : dn(c->SW), b2 = bf ? pl(c->HC_p) : dn(w.HC);
+    // BF16x3 reads the transposed planes of SC, HC (k-contiguous); the others read SC, HC by rows
+    GemmDesc d{compute, bf ? T_BF16P : T_F64, ot, et, et, KC, bf ? KC : RC, 0, 1};
+    GemmOp op = make_op2(M, N, M, bf ? pl(c->HW_p) : dn(c->HW), M, bf ? pl(c->SCt_p) : dn(w.SC),
+                         bf ? M : N, G, N, -4.0, w.HC, N, 8.0);
+    const Opnd a2 = bf ? pl(c->SW_p) : dn(c->SW), b2 = bf ? pl(c->HCt_p) : dn(w.HC);
     op.nseg = 2;
     op.A[1] = a2.p; op.Alo[1] = a2.lo; op.lda[1] = M;
-    op.B[1] = b2.p; op.Blo[1] = b2.lo; op.ldb[1] = N;
+    op.B[1] = b2.p; op.Blo[1] = b2.lo; op.ldb[1] = bf ? M : N;
     op.K[1] = M;
     TRY(gemm(c, d, &op, 1, done));
   }
@@ -650,10 +662,7 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
                         c->stream));
   TRY(prof_mark(c));
   HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, w.SD, mn, c->st, c->stream));
-  if (bf) {
-    TRY(split(c, w.HC, c->HC_p, mn));
-    TRY(split(c, w.SC, c->SC_p, mn));
-  }
+  if (bf) TRY(split_state(c, w.HC, w.SC));
   HIPCHK(c, update_subspace(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
                             trace, c->stream));
   TRY(prof_mark(c));
@@ -746,8 +755,7 @@ int resync_fp64(omm_ctx* c) {
                     make_op(M, M, N, w.SC, N, w.C, N, c->SW, M)};
   TRY(gemm(c, d, ops2, 2, nullptr));
   // the BF16x3 products read HC and SC through their planes
-  TRY(split(c, w.HC, c->HC_p, (int64_t)M * N, false));
-  TRY(split(c, w.SC, c->SC_p, (int64_t)M * N, false));
+  TRY(split_state(c, w.HC, w.SC, false));
   const int it = c->st_host->iter;
   TRY(ensure_trace(c, c->trace_off + it + 2));
   HIPCHK(c, energy_init(c->HW, c->SW, M, c->partials, c->st, c->trace + c->trace_off + it,
@@ -847,8 +855,7 @@ int minimize_impl(omm_ctx* c, const double* C0, bool C0_device, double eta, doub
   if (mixed64) {
     TRY(phase_begin<double>(c, c->w64, CF64, c->Hs, c->S, tol, 0));
     TRY(alloc_iter_planes(c));
-    TRY(split(c, c->w64.HC, c->HC_p, (int64_t)mn, false));
-    TRY(split(c, c->w64.SC, c->SC_p, (int64_t)mn, false));
+    TRY(split_state(c, c->w64.HC, c->w64.SC, false));
     c->phase_prec = OMM_BF16X3;
     c->phase_mixed64 = true;
     c->since_resync = 0;
@@ -966,7 +973,7 @@ int omm_destroy(omm_ctx* c) {
   free_work(c->w64);
   free_work(c->w32);
   for (Plane* p : {&c->Hs_p, &c->S_p, &c->P_p, &c->C_p, &c->HC_p, &c->SC_p, &c->G_p, &c->D_p,
-                   &c->HD_p, &c->SD_p, &c->HW_p, &c->SW_p})
+                   &c->HD_p, &c->SD_p, &c->HW_p, &c->SW_p, &c->HCt_p, &c->SCt_p})
     free_plane(*p);
   dfree(c->HW); dfree(c->SW); dfree(c->H1); dfree(c->S1); dfree(c->H2); dfree(c->S2);
   dfree(c->partials); dfree(c->ws); dfree(c->st); dfree(c->flags); dfree(c->trace);

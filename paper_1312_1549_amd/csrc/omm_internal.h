@@ -85,6 +85,11 @@ hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, 
                       const DevState* st, hipStream_t s);
 hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t n,
                       const DevState* st, hipStream_t s);
+// Planes of the transpose: src is rows x cols row-major, hi/lo are cols x rows row-major.
+hipError_t split_bf16_t(const float* src, unsigned short* hi, unsigned short* lo, int rows,
+                        int cols, const DevState* st, hipStream_t s);
+hipError_t split_bf16_t(const double* src, unsigned short* hi, unsigned short* lo, int rows,
+                        int cols, const DevState* st, hipStream_t s);
 hipError_t convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 hipError_t copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
 hipError_t validate_symmetric(const double* A, int64_t n, double rtol, int* flags, hipStream_t s);

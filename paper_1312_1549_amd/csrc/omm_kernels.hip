@@ -86,6 +86,31 @@ __global__ void k_split(const T* src, unsigned short* hi, unsigned short* lo, in
   }
 }
 
+// Transposing split through a 32 x 33 LDS tile: dst (cols x rows) = planes of src^T.
+template <typename T>
+__global__ void k_split_t(const T* src, unsigned short* hi, unsigned short* lo, int rows, int cols,
+                          const DevState* st) {
+  if (st && st->done) return;
+  __shared__ T t[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int gr = r0 + r, gc = c0 + tx;
+    t[r][tx] = (gr < rows && gc < cols) ? src[(int64_t)gr * cols + gc] : (T)0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int oc = c0 + r, orow = r0 + tx;  // output row oc (a source column), column orow
+    if (oc < cols && orow < rows) {
+      const double v = (double)t[tx][r];
+      const unsigned short hb = bf16_bits((float)v);
+      const int64_t o = (int64_t)oc * rows + orow;
+      hi[o] = hb;
+      lo[o] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+    }
+  }
+}
+
 int ew_blocks(int64_t n) {
   int64_t b = (n + NT - 1) / NT;
   if (b > 8192) b = 8192;
@@ -597,6 +622,20 @@ hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, 
 hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t n,
                       const DevState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_split<double>, dim3(ew_blocks(n / 4 + 1)), dim3(NT), 0, s, src, hi, lo, n, st);
+  return hipGetLastError();
+}
+
+hipError_t split_bf16_t(const float* src, unsigned short* hi, unsigned short* lo, int rows,
+                        int cols, const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_split_t<float>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0, s, src,
+                     hi, lo, rows, cols, st);
+  return hipGetLastError();
+}
+
+hipError_t split_bf16_t(const double* src, unsigned short* hi, unsigned short* lo, int rows,
+                        int cols, const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_split_t<double>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0, s,
+                     src, hi, lo, rows, cols, st);
   return hipGetLastError();
 }
 
