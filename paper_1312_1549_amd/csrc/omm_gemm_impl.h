@@ -150,8 +150,57 @@ struct Stager {
     if constexpr (MODE == CF64) rd[idx] = v; else rf[idx] = (float)v;
   }
 
+  // Whole tile in bounds with aligned rows: unconditional vector loads (one uniform branch per
+  // tile instead of one per vector).
+  __device__ __forceinline__ bool full_tile(int r0, int rmax, int k0, int ke, bool vec_ok) const {
+    // uniform across the block: make it a scalar branch
+    const int f = vec_ok && r0 + R <= rmax && k0 + BK <= ke;
+    return __builtin_amdgcn_readfirstlane(f) != 0;
+  }
+
+  __device__ __forceinline__ void load_full(const void* X, const void* Xlo, int64_t ld, int r0, int k0,
+                                            int tid) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      int r, k;
+      coords(tid, v, r, k);
+      const int gr = r0 + r, gk = k0 + k;
+      const int64_t off = LAYOUT == KC ? (int64_t)gr * ld + gk : (int64_t)gk * ld + gr;
+      if constexpr (PL) {
+        ph[v] = *reinterpret_cast<const u16x8*>(static_cast<const unsigned short*>(X) + off);
+        pq[v] = *reinterpret_cast<const u16x8*>(static_cast<const unsigned short*>(Xlo) + off);
+      } else if (LAYOUT == KC) {
+        const TS* p = static_cast<const TS*>(X) + off;
+        if constexpr (sizeof(TS) == 8) {
+#pragma unroll
+          for (int u = 0; u < VEC; u += 2) {
+            const double2 q = *reinterpret_cast<const double2*>(p + u);
+            put(v * VEC + u, q.x);
+            put(v * VEC + u + 1, q.y);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; u += 4) {
+            const float4 q = *reinterpret_cast<const float4*>(p + u);
+            put(v * VEC + u, q.x);
+            put(v * VEC + u + 1, q.y);
+            put(v * VEC + u + 2, q.z);
+            put(v * VEC + u + 3, q.w);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) put(v * VEC + u, (double)ldg<TS>(X, off + u));
+      }
+    }
+  }
+
   __device__ __forceinline__ void load(const void* X, const void* Xlo, int64_t ld, int r0, int rmax,
                                        int k0, int ke, int tid, bool vec_ok) {
+    if (full_tile(r0, rmax, k0, ke, vec_ok)) {
+      load_full(X, Xlo, ld, r0, k0, tid);
+      return;
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       int r, k;
