@@ -19,7 +19,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 BUILD = ROOT / "_build"
 LIB = PKG / "libomm.so"
-SOURCES = ["omm_gemm_bf16x3.hip", "omm_gemm_f32.hip", "omm_gemm_f64.hip", "omm_gemm.hip",
+SOURCES = ["omm_gemm_bf16x3.hip", "omm_gemm_bf16x2.hip", "omm_gemm_f32.hip", "omm_gemm_f64.hip", "omm_gemm.hip",
            "omm_kernels.hip", "omm_precon.hip", "omm_context.hip", "omm_batch.hip"]
 HEADERS = [CSRC / "omm_internal.h", CSRC / "omm_gemm_impl.h", ROOT / "include" / "omm.h"]
 

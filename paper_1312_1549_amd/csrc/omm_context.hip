@@ -101,6 +101,10 @@ struct omm_ctx {
   int phase_k = 0;            // line searches launched in the active phase
   int trace_off = 0;          // offset of the active phase in the energy trace
   int iters_before = 0;       // line searches of earlier phases of the last minimize call
+  // hipGraph of two line searches of the active phase (replayed after the first two)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_parity = -1;  // phase_k & 1 at capture
   // profiling: HIP events around each stage of every launched line search
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -253,10 +257,13 @@ void tune_save_locked() {
   fclose(f);
 }
 
+void drop_graph(omm_ctx* c);
+
 int ensure_ws(omm_ctx* c, const GemmOp* ops, int nops, int splitk) {
   if (splitk <= 1) return OMM_OK;
   const size_t need = gemm_splitk_ws_bytes(ops, nops, splitk);
   if (need > c->ws_bytes) {
+    drop_graph(c);  // a captured graph holds the old workspace address
     dfree(c->ws);
     c->ws_bytes = 0;
     TRY(dalloc(c, &c->ws, need / sizeof(double) + 1));
@@ -383,6 +390,7 @@ int ensure_inputs(omm_ctx* c) {
 }
 
 void invalidate(omm_ctx* c) {
+  drop_graph(c);
   c->phase_active = false;
   c->phase_mixed64 = false;
   c->hsp_valid = false;
@@ -624,22 +632,26 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     TRY(gemm(c, d, &op, 1, done));
   }
   TRY(prof_mark(c));
+  // BF16x3: the preconditioner is applied as its bf16 rounding (the hi plane of P, a symmetric
+  // matrix of its own) and the search direction is rounded to bf16 when it is formed, so every
+  // product with P or D takes two MFMA products instead of three (same accuracy: the rounded
+  // operand is exact).
+  const int cP = bf ? CBF16X2B : compute, cD = bf ? CBF16X2A : compute;
   T* PG = G;
   if (c->p_kind > 0) {
     if (bf) TRY(split(c, G, c->G_p, mn));
-    GemmDesc d{compute, ot, ot, et, et, KC, KC, 0, 1};
+    GemmDesc d{cP, ot, ot, et, et, KC, KC, 0, 1};
     GemmOp op = make_op2(M, N, N, bf ? pl(c->G_p) : dn(G), N, bf ? pl(c->P_p) : dn(P), N, w.PG, N);
     TRY(gemm(c, d, &op, 1, done));
     PG = w.PG;
   }
   TRY(prof_mark(c));
   HIPCHK(c, beta_and_direction<T>(G, PG, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials, c->st,
-                                  c->stream));
-  if (bf) TRY(split(c, w.D, c->D_p, mn));
+                                  c->stream, bf ? c->D_p.hi : nullptr));
   TRY(prof_mark(c));
   const Opnd Dop = bf ? pl(c->D_p) : dn(w.D);
   {
-    GemmDesc d{compute, ot, ot, et, et, KC, KC, 0, 1};
+    GemmDesc d{cD, ot, ot, et, et, KC, KC, 0, 1};
     GemmOp ops[2] = {make_op2(M, N, N, Dop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HD, N),
                      make_op2(M, N, N, Dop, N, bf ? pl(c->S_p) : dn(S), N, w.SD, N)};
     TRY(gemm(c, d, ops, 2, done));
@@ -650,7 +662,7 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   }
   TRY(prof_mark(c));
   {
-    GemmDesc d{compute, ot, ot, T_F64, T_F64, KC, KC, 0, 1};
+    GemmDesc d{cD, ot, ot, T_F64, T_F64, KC, KC, 0, 1};
     GemmOp ops[4] = {make_op2(M, M, N, Dop, N, bf ? pl(c->HC_p) : dn(w.HC), N, c->H1, M),
                      make_op2(M, M, N, Dop, N, bf ? pl(c->SC_p) : dn(w.SC), N, c->S1, M),
                      make_op2(M, M, N, Dop, N, bf ? pl(c->HD_p) : dn(w.HD), N, c->H2, M),
@@ -683,10 +695,45 @@ int ensure_trace(omm_ctx* c, int need) {
     HIPCHK(c, hipMemcpyAsync(t, c->trace, c->trace_cap * sizeof(double), hipMemcpyDeviceToDevice,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);  // a captured graph holds the old trace address
     dfree(c->trace);
   }
   c->trace = t;
   c->trace_cap = need;
+  return OMM_OK;
+}
+
+void drop_graph(omm_ctx* c) {
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_parity = -1;
+}
+
+bool graphs_enabled(omm_ctx* c) {
+  const char* e = getenv("OMM_GRAPH");
+  return !c->prof && !(e && e[0] == '0');
+}
+
+// Captures line searches k and k+1 (same buffers every time; only the parity of k matters).
+template <typename T>
+int capture_pair(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, const T* P, int k,
+                 double* trace) {
+  drop_graph(c);
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int r = line_search_iteration<T>(c, w, compute, Hs, S, P, k, trace);
+  if (r == OMM_OK) r = line_search_iteration<T>(c, w, compute, Hs, S, P, k + 1, trace);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (r != OMM_OK) {
+    if (g) hipGraphDestroy(g);
+    return r;
+  }
+  HIPCHK(c, e);
+  c->graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  c->graph_parity = k & 1;
   return OMM_OK;
 }
 
@@ -699,6 +746,7 @@ int phase_begin(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, do
   init.max_iter = 0;
   HIPCHK(c, hipMemcpyAsync(c->st, &init, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
   TRY(ensure_trace(c, trace_off + 2));
+  drop_graph(c);
   TRY(initial_products<T>(c, w, compute, Hs, S, c->trace + trace_off));
   TRY(read_state(c));
   c->phase_active = true;
@@ -726,10 +774,26 @@ int phase_iterate(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, 
   // return immediately.
   const int check = c->N >= 4096 ? 2 : 8;
   if (count > 0) {
-    for (int k = 0; k < count; ++k) {
-      TRY(line_search_iteration<T>(c, w, compute, Hs, S, P, c->phase_k, trace));
-      c->phase_k += 1;
-      if ((k + 1) % check == 0 || k + 1 == count) {
+    // The first two line searches of a phase run eagerly (every GEMM shape is tuned and its
+    // workspace allocated); after that pairs of line searches replay one captured graph.
+    const bool graphs = graphs_enabled(c);
+    int since = 0;
+    for (int k = 0; k < count;) {
+      if (graphs && c->phase_k >= 2 && count - k >= 2) {
+        if (!c->graph_exec || c->graph_parity != (c->phase_k & 1))
+          TRY(capture_pair<T>(c, w, compute, Hs, S, P, c->phase_k, trace));
+        HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+        k += 2;
+        c->phase_k += 2;
+        since += 2;
+      } else {
+        TRY(line_search_iteration<T>(c, w, compute, Hs, S, P, c->phase_k, trace));
+        k += 1;
+        c->phase_k += 1;
+        since += 1;
+      }
+      if (since >= check || k == count) {
+        since = 0;
         TRY(read_state(c));
         if (h->done != 0) break;
       }
@@ -968,6 +1032,7 @@ int omm_create(int64_t N, int64_t M, omm_ctx** out) {
 int omm_destroy(omm_ctx* c) {
   if (!c) return OMM_E_ARG;
   hipStreamSynchronize(c->stream);
+  drop_graph(c);
   dfree(c->H); dfree(c->S); dfree(c->T); dfree(c->Hs); dfree(c->P);
   dfree(c->Hs32); dfree(c->S32); dfree(c->P32);
   free_work(c->w64);
@@ -1250,6 +1315,7 @@ int omm_iterate(omm_ctx* c, int count, double tol) {
 int omm_set_profiling(omm_ctx* c, int on) {
   if (!c) return OMM_E_ARG;
   TRY(prof_collect(c));
+  drop_graph(c);
   c->prof = on != 0;
   c->ev_used = 0;
   for (int i = 0; i < NSTAGE; ++i) c->stage_ms[i] = 0.0;

@@ -8,6 +8,7 @@ namespace gemm_detail {
 gemm_fn pick_f64(const GemmDesc& d);
 gemm_fn pick_f32(const GemmDesc& d);
 gemm_fn pick_bf16x3(const GemmDesc& d);
+gemm_fn pick_bf16x2(const GemmDesc& d);
 grouped_fn pick_grouped_f32(const GemmDesc& d);
 
 namespace {
@@ -45,6 +46,7 @@ bool gemm_supported(const GemmDesc& d) {
   if (d.compute == CF64) return pick_f64(d) != nullptr;
   if (d.compute == CF32) return pick_f32(d) != nullptr;
   if (d.compute == CBF16X3) return pick_bf16x3(d) != nullptr;
+  if (d.compute == CBF16X2A || d.compute == CBF16X2B) return pick_bf16x2(d) != nullptr;
   return false;
 }
 
@@ -77,6 +79,7 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
   if (d.compute == CF64) fn = pick_f64(d);
   else if (d.compute == CF32) fn = pick_f32(d);
   else if (d.compute == CBF16X3) fn = pick_bf16x3(d);
+  else if (d.compute == CBF16X2A || d.compute == CBF16X2B) fn = pick_bf16x2(d);
   if (!fn) return hipErrorInvalidValue;
   const int bm = tile_bm(d.tile, d.compute), bn = tile_bn(d.tile, d.compute);
   const int tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);

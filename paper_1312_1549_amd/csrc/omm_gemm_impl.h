@@ -16,8 +16,10 @@
 //   CBF16X3  v_mfma_f32_16x16x32_bf16 on a hi/lo split of each operand (a = hi + lo,
 //            hi = bf16(a), lo = bf16(a - hi)); three products lo*hi + hi*lo + hi*hi per K step,
 //            FP32 accumulation. Lane l holds row l%16, k 8(l/16)..8(l/16)+7; result rows
-//            4(l/16) + r. The split happens while a tile is staged, so operands stay FP32/FP64
-//            in HBM.
+//            4(l/16) + r. Operands are either pre-split bf16 planes or FP32/FP64 values split
+//            while a tile is staged.
+//   CBF16X2A / CBF16X2B  the same with A (B) exactly representable in bf16: only its hi plane
+//            is staged and two products remain (hi*lo + hi*hi).
 #pragma once
 
 #include <type_traits>
@@ -108,6 +110,10 @@ struct ModeTraits<CBF16X3> {
   static constexpr int VEC = 8;  // 8 elements -> one 16-byte hi and one 16-byte lo LDS write
   static constexpr int PAD = 8;
 };
+template <>
+struct ModeTraits<CBF16X2A> : ModeTraits<CBF16X3> {};
+template <>
+struct ModeTraits<CBF16X2B> : ModeTraits<CBF16X3> {};
 
 // Global -> register staging of one operand tile (R rows x BK), `NV` vectors of VEC per thread.
 // KC: vector = VEC consecutive k of one row. RC: vector = VEC consecutive rows of one k.
@@ -121,19 +127,23 @@ __device__ __forceinline__ int lds_off(int r, int k) {
   else return r * RS + k;
 }
 
-template <int MODE, typename TS, int LAYOUT, int R, int BK, int NT, bool SWZ = false>
+// ONE: the operand is a single bf16 plane (exact values): the lo plane is neither read nor
+// staged.
+template <int MODE, typename TS, int LAYOUT, int R, int BK, int NT, bool SWZ = false,
+          bool ONE = false>
 struct Stager {
   static constexpr int VEC = ModeTraits<MODE>::VEC;
   static constexpr int NV = R * BK / VEC / NT;
   static_assert(R * BK % (VEC * NT) == 0, "tile not divisible among threads");
   static constexpr bool PL = std::is_same<TS, unsigned short>::value;
-  static_assert(!PL || MODE == CBF16X3, "bf16 planes feed the BF16x3 mode only");
+  static_assert(!PL || is_bf16_mode(MODE), "bf16 planes feed the BF16x3 modes only");
+  static_assert(!ONE || PL, "a single-plane operand is a bf16 plane");
   typedef typename ModeTraits<MODE>::lds_t lds_t;
-  static_assert(!SWZ || (MODE == CBF16X3 && BK == 32), "swizzle: BF16x3 with BK = 32 only");
+  static_assert(!SWZ || (is_bf16_mode(MODE) && BK == 32), "swizzle: BF16x3 with BK = 32 only");
   static constexpr int RS = SWZ ? BK : BK + ModeTraits<MODE>::PAD;  // LDS row stride (elements)
   float rf[(MODE == CF64 || PL) ? 1 : NV * VEC];
   double rd[MODE == CF64 ? NV * VEC : 1];
-  u16x8 ph[PL ? NV : 1], pq[PL ? NV : 1];
+  u16x8 ph[PL ? NV : 1], pq[PL && !ONE ? NV : 1];
 
   __device__ __forceinline__ void coords(int tid, int v, int& r, int& k) const {
     const int e = tid + v * NT;
@@ -168,7 +178,8 @@ struct Stager {
       const int64_t off = LAYOUT == KC ? (int64_t)gr * ld + gk : (int64_t)gk * ld + gr;
       if constexpr (PL) {
         ph[v] = *reinterpret_cast<const u16x8*>(static_cast<const unsigned short*>(X) + off);
-        pq[v] = *reinterpret_cast<const u16x8*>(static_cast<const unsigned short*>(Xlo) + off);
+        if constexpr (!ONE)
+          pq[v] = *reinterpret_cast<const u16x8*>(static_cast<const unsigned short*>(Xlo) + off);
       } else if (LAYOUT == KC) {
         const TS* p = static_cast<const TS*>(X) + off;
         if constexpr (sizeof(TS) == 8) {
@@ -213,26 +224,26 @@ struct Stager {
           const int64_t off = (int64_t)gr * ld + gk;
           if (vec_ok && gr < rmax && gk + 8 <= ke) {
             ph[v] = *reinterpret_cast<const u16x8*>(hp + off);
-            pq[v] = *reinterpret_cast<const u16x8*>(lp + off);
+            if constexpr (!ONE) pq[v] = *reinterpret_cast<const u16x8*>(lp + off);
           } else {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
               const bool in = gr < rmax && gk + u < ke;
               ph[v][u] = in ? hp[off + u] : (unsigned short)0;
-              pq[v][u] = in ? lp[off + u] : (unsigned short)0;
+              if constexpr (!ONE) pq[v][u] = in ? lp[off + u] : (unsigned short)0;
             }
           }
         } else {
           const int64_t off = (int64_t)gk * ld + gr;
           if (vec_ok && gk < ke && gr + 8 <= rmax) {
             ph[v] = *reinterpret_cast<const u16x8*>(hp + off);
-            pq[v] = *reinterpret_cast<const u16x8*>(lp + off);
+            if constexpr (!ONE) pq[v] = *reinterpret_cast<const u16x8*>(lp + off);
           } else {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
               const bool in = gr + u < rmax && gk < ke;
               ph[v][u] = in ? hp[off + u] : (unsigned short)0;
-              pq[v][u] = in ? lp[off + u] : (unsigned short)0;
+              if constexpr (!ONE) pq[v][u] = in ? lp[off + u] : (unsigned short)0;
             }
           }
         }
@@ -281,15 +292,15 @@ struct Stager {
       if constexpr (PL) {
         if (LAYOUT == KC) {
           *reinterpret_cast<u16x8*>(s0 + lds_off<SWZ, RS>(r, k)) = ph[v];
-          *reinterpret_cast<u16x8*>(s1 + lds_off<SWZ, RS>(r, k)) = pq[v];
+          if constexpr (!ONE) *reinterpret_cast<u16x8*>(s1 + lds_off<SWZ, RS>(r, k)) = pq[v];
         } else {
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             s0[lds_off<SWZ, RS>(r + u, k)] = ph[v][u];
-            s1[lds_off<SWZ, RS>(r + u, k)] = pq[v][u];
+            if constexpr (!ONE) s1[lds_off<SWZ, RS>(r + u, k)] = pq[v][u];
           }
         }
-      } else if constexpr (MODE == CBF16X3) {
+      } else if constexpr (is_bf16_mode(MODE)) {
         if (LAYOUT == KC) {
           u16x8 h, l;
 #pragma unroll
@@ -351,17 +362,20 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
                                           double* ws, int z, int nops) {
   constexpr int NT = WM * WN * 64;
   constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
-  typedef Stager<MODE, TA, LA, BM, BK, NT, SWZ> SA;
-  typedef Stager<MODE, TB, LB, BN, BK, NT, SWZ> SB;
+  constexpr bool ONE_A = MODE == CBF16X2A, ONE_B = MODE == CBF16X2B;
+  typedef Stager<MODE, TA, LA, BM, BK, NT, SWZ, ONE_A> SA;
+  typedef Stager<MODE, TB, LB, BN, BK, NT, SWZ, ONE_B> SB;
   typedef typename ModeTraits<MODE>::lds_t lds_t;
   constexpr int RS = SA::RS;
-  constexpr int NBUF = MODE == CBF16X3 ? 2 : 1;  // hi + lo planes
+  // LDS planes per operand: hi + lo, or hi alone for a single-plane operand
+  constexpr int NBA = is_bf16_mode(MODE) && !ONE_A ? 2 : 1;
+  constexpr int NBB = is_bf16_mode(MODE) && !ONE_B ? 2 : 1;
   typedef typename AccT<MODE>::type acc_t;
 
   const int m0 = tm * BM, n0 = tn * BN;
 
-  __shared__ __attribute__((aligned(16))) lds_t As[2][NBUF][BM * RS];
-  __shared__ __attribute__((aligned(16))) lds_t Bs[2][NBUF][BN * RS];
+  __shared__ __attribute__((aligned(16))) lds_t As[2][NBA][BM * RS];
+  __shared__ __attribute__((aligned(16))) lds_t Bs[2][NBB][BN * RS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
@@ -391,8 +405,8 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
     __syncthreads();  // previous segment's readers are done with the buffers
     sa.load(A, Al, lda, m0, op.M, kb, ke, tid, va);
     sb.load(B, Bl, ldb, n0, op.N, kb, ke, tid, vb);
-    sa.store(As[0][0], As[0][NBUF - 1], tid);
-    sb.store(Bs[0][0], Bs[0][NBUF - 1], tid);
+    sa.store(As[0][0], As[0][NBA - 1], tid);
+    sb.store(Bs[0][0], Bs[0][NBB - 1], tid);
     __syncthreads();
     int buf = 0;
     for (int k0 = kb; k0 < ke; k0 += BK) {
@@ -403,9 +417,17 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
       }
       const lds_t* a0 = As[buf][0];
       const lds_t* b0 = Bs[buf][0];
-      if constexpr (MODE == CBF16X3) {
-        const lds_t* a1 = As[buf][NBUF - 1];
-        const lds_t* b1 = Bs[buf][NBUF - 1];
+      if constexpr (is_bf16_mode(MODE)) {
+        const lds_t* a1 = As[buf][NBA - 1];
+        const lds_t* b1 = Bs[buf][NBB - 1];
+        // lo*hi terms first, hi*hi last (smaller terms enter the FP32 accumulator first)
+        auto prod = [&](const bf8& ah, const bf8& al, const bf8& bh, const bf8& bl, f4 c) {
+          if constexpr (!ONE_A)
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+          if constexpr (!ONE_B)
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+          return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+        };
         const int kof = 8 * (lane >> 4);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 32) {
@@ -420,18 +442,14 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
             for (int j = 0; j < TN; ++j) {
               const int r = wn * TN * 16 + j * 16 + (lane & 15);
               bh[j] = frag(b0, r);
-              bl[j] = frag(b1, r);
+              bl[j] = ONE_B ? bh[j] : frag(b1, r);
             }
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
               const int r = wm * TM * 16 + i * 16 + (lane & 15);
-              const bf8 ah = frag(a0, r), al = frag(a1, r);
+              const bf8 ah = frag(a0, r), al = ONE_A ? ah : frag(a1, r);
 #pragma unroll
-              for (int j = 0; j < TN; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-              }
+              for (int j = 0; j < TN; ++j) acc[i][j] = prod(ah, al, bh[j], bl[j], acc[i][j]);
             }
           } else {
             bf8 ah[TM], al[TM];
@@ -439,18 +457,14 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
             for (int i = 0; i < TM; ++i) {
               const int r = wm * TM * 16 + i * 16 + (lane & 15);
               ah[i] = frag(a0, r);
-              al[i] = frag(a1, r);
+              al[i] = ONE_A ? ah[i] : frag(a1, r);
             }
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
               const int r = wn * TN * 16 + j * 16 + (lane & 15);
-              const bf8 bh = frag(b0, r), bl = frag(b1, r);
+              const bf8 bh = frag(b0, r), bl = ONE_B ? bh : frag(b1, r);
 #pragma unroll
-              for (int i = 0; i < TM; ++i) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
-              }
+              for (int i = 0; i < TM; ++i) acc[i][j] = prod(ah[i], al[i], bh, bl, acc[i][j]);
             }
           }
         }
@@ -470,8 +484,8 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
         }
       }
       if (more) {
-        sa.store(As[buf ^ 1][0], As[buf ^ 1][NBUF - 1], tid);
-        sb.store(Bs[buf ^ 1][0], Bs[buf ^ 1][NBUF - 1], tid);
+        sa.store(As[buf ^ 1][0], As[buf ^ 1][NBA - 1], tid);
+        sb.store(Bs[buf ^ 1][0], Bs[buf ^ 1][NBB - 1], tid);
       }
       __syncthreads();
       buf ^= 1;
@@ -553,25 +567,25 @@ typedef void (*grouped_fn)(GroupedArgs);
 // swizzled unpadded LDS); FP64/FP32: 128x128 with 2 workgroups per CU.
 constexpr int NTILES = 5;
 inline int tile_bm(int t, int mode) {
-  return t == 1 ? 64 : (t == 2 || (t == 4 && mode == CBF16X3) ? 256 : 128);
+  return t == 1 ? 64 : (t == 2 || (t == 4 && is_bf16_mode(mode)) ? 256 : 128);
 }
 inline int tile_bn(int t, int mode) {
-  return t == 1 ? 64 : (t == 3 || (t == 4 && mode == CBF16X3) ? 256 : 128);
+  return t == 1 ? 64 : (t == 3 || (t == 4 && is_bf16_mode(mode)) ? 256 : 128);
 }
 inline int tile_threads(int t, int mode) {
-  return (t == 2 || t == 3 || (t == 4 && mode == CBF16X3)) ? 512 : 256;
+  return (t == 2 || t == 3 || (t == 4 && is_bf16_mode(mode))) ? 512 : 256;
 }
 
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB>
 grouped_fn pick_grouped_tile(int tile) {
-  constexpr int BK = MODE == CBF16X3 ? 32 : 16;
+  constexpr int BK = is_bf16_mode(MODE) ? 32 : 16;
   switch (tile) {
     case 0: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 4, 4, BK, 1>;
     case 1: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 2, 2, BK, 2>;
     case 2: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 4, 2, 4, 4, BK, 1>;
     case 3: return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 4, 4, BK, 1>;
     case 4:
-      if constexpr (MODE == CBF16X3)
+      if constexpr (is_bf16_mode(MODE))
         return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 8, 4, BK, 1, true>;
       else
         return gemm_grouped_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 4, 4, BK, 2>;
@@ -581,14 +595,14 @@ grouped_fn pick_grouped_tile(int tile) {
 
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB>
 gemm_fn pick_tile(int tile) {
-  constexpr int BK = MODE == CBF16X3 ? 32 : 16;
+  constexpr int BK = is_bf16_mode(MODE) ? 32 : 16;
   switch (tile) {
     case 0: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 4, 4, BK, 1>;
     case 1: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 2, 2, BK, 2>;
     case 2: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 4, 2, 4, 4, BK, 1>;
     case 3: return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 4, 4, BK, 1>;
     case 4:
-      if constexpr (MODE == CBF16X3)
+      if constexpr (is_bf16_mode(MODE))
         return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 8, 4, BK, 1, true>;
       else
         return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 4, 4, BK, 2>;

@@ -28,7 +28,11 @@ struct DevState {
 //   RC: element (r, k) at X[k * ld + r]   (r contiguous)
 enum Layout : int { KC = 0, RC = 1 };
 
-enum Compute : int { CF64 = 0, CF32 = 1, CBF16X3 = 2 };
+// CBF16X3: both operands are hi/lo bf16 plane pairs, three products per K step (lo*hi, hi*lo,
+// hi*hi). CBF16X2A / CBF16X2B: A (B) holds exact bf16 values in its hi plane alone, so two
+// products (hi*lo + hi*hi) carry the same accuracy.
+enum Compute : int { CF64 = 0, CF32 = 1, CBF16X3 = 2, CBF16X2A = 3, CBF16X2B = 4 };
+constexpr bool is_bf16_mode(int m) { return m >= CBF16X3; }
 
 // T_BF16P: a pair of bf16 planes (hi, lo) with a = hi + lo, pointers in A/Alo (B/Blo).
 enum ElemType : int { T_F64 = 0, T_F32 = 1, T_BF16P = 2 };
@@ -99,9 +103,12 @@ hipError_t symmetrize(double* A, int64_t n, hipStream_t s);
 hipError_t energy_init(const double* HW, const double* SW, int M, double* partials, DevState* st,
                        double* trace, hipStream_t s);
 
+// Polak-Ribiere beta and D = -PG + beta D. With `hi` non-null D is rounded to bf16 in place and
+// its bits are written to `hi` (the single-plane operand of the two-product GEMMs).
 template <typename T>
 hipError_t beta_and_direction(const T* G, const T* PG, const T* Gprev, T* D, int64_t n, int first,
-                              double* partials, DevState* st, hipStream_t s);
+                              double* partials, DevState* st, hipStream_t s,
+                              unsigned short* hi = nullptr);
 
 hipError_t line_search(const double* HW, const double* SW, const double* H1, const double* S1,
                        const double* H2, const double* S2, int M, double* partials, DevState* st,

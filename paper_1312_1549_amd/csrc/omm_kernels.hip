@@ -270,6 +270,21 @@ __global__ void k_direction(const T* PG, T* D, int64_t n, int first, const DevSt
   b_direction(PG, D, n, first, st, blockIdx.x, gridDim.x);
 }
 
+// The same direction rounded to bf16: D keeps the rounded values (exact in T) and `hi` their bf16
+// bits, so the products with D need no lo plane and the CG update moves along exactly this D.
+template <typename T>
+__global__ void k_direction_bf16(const T* PG, T* D, unsigned short* hi, int64_t n, int first,
+                                 const DevState* st) {
+  if (st->done) return;
+  const double beta = st->beta;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    const double d = first ? -(double)PG[i] : -(double)PG[i] + beta * (double)D[i];
+    const unsigned short hb = bf16_bits((float)d);
+    hi[i] = hb;
+    D[i] = (T)__uint_as_float(((unsigned int)hb) << 16);
+  }
+}
+
 // ---- quartic coefficients (Eq. 13) --------------------------------------------------------------
 // Sums (index order used by the finalizer):
 //  0 Tr HW   1 Tr H'   2 Tr H''
@@ -671,19 +686,24 @@ hipError_t energy_init(const double* HW, const double* SW, int M, double* partia
 
 template <typename T>
 hipError_t beta_and_direction(const T* G, const T* PG, const T* Gprev, T* D, int64_t n, int first,
-                              double* partials, DevState* st, hipStream_t s) {
+                              double* partials, DevState* st, hipStream_t s, unsigned short* hi) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_pr_partials<T>, dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first, partials,
                      st);
   hipLaunchKernelGGL(k_pr_final, dim3(1), dim3(NT), 0, s, partials, nb, first, st);
-  hipLaunchKernelGGL(k_direction<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, n, first, st);
+  if (hi)
+    hipLaunchKernelGGL(k_direction_bf16<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, hi, n, first,
+                       st);
+  else
+    hipLaunchKernelGGL(k_direction<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, n, first, st);
   return hipGetLastError();
 }
 template hipError_t beta_and_direction<double>(const double*, const double*, const double*,
                                                double*, int64_t, int, double*, DevState*,
-                                               hipStream_t);
+                                               hipStream_t, unsigned short*);
 template hipError_t beta_and_direction<float>(const float*, const float*, const float*, float*,
-                                              int64_t, int, double*, DevState*, hipStream_t);
+                                              int64_t, int, double*, DevState*, hipStream_t,
+                                              unsigned short*);
 
 hipError_t line_search(const double* HW, const double* SW, const double* H1, const double* S1,
                        const double* H2, const double* S2, int M, double* partials, DevState* st,

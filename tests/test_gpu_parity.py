@@ -179,6 +179,74 @@ def test_runs_are_bitwise_reproducible(lib_ok, c2, precision):
     assert np.array_equal(traces[0], traces[1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_odd_sizes_take_the_unvectorized_paths(lib_ok, precision):
+    """N = 33 (11 atoms x 3 orbitals), M = 7: rows of odd length defeat every vector load, so
+    the predicated scalar staging paths of all GEMM layouts are exercised."""
+    rng = np.random.default_rng(33)
+    pos = lattice_positions((3, 2, 2), 2.5, 11)
+    pos = pos + rng.uniform(-0.2, 0.2, size=pos.shape)
+    s = make_system(pos, 3, 6.0, 7, rng, name="odd", eta=0.5, tau=10.0, seed=33)
+    C0 = start_coefficients(s.S, s.M, 34)
+    w = brute.generalized_eigh_lapack(s.H, s.S)[0]
+    eta = w[s.M] - 0.25 * (w[s.M] - w[s.M - 1])
+    _say(f"odd sizes N={s.N} M={s.M} {precision}")
+    solver, status = _run(lib_ok, s, C0, eta, 10.0, 1e-13, 5000, precision=precision,
+                          refine=precision != "fp32")
+    E_ref = brute.closed_form_energy(w, s.M, eta)
+    tolr = 1e-5 if precision == "fp32" else 1e-10
+    assert abs(solver.energy() - E_ref) <= tolr * abs(E_ref)
+    if precision == "fp64":
+        ref = oracle.minimize(s.H, s.S, s.T, C0, eta, 10.0, 0.0, 20)
+        np.testing.assert_allclose(solver.energy_trace()[:21], ref.energies[:21], rtol=1e-10)
+
+
+def test_fully_occupied_limit(lib_ok):
+    """M = N: every eigenvector is occupied; with eta above the whole spectrum the minimum is
+    2 sum_i (eps_i - eta) and SW = I (C^T C = S^-1 in row form)."""
+    rng = np.random.default_rng(40)
+    pos = lattice_positions((2, 2, 2), 2.5)
+    pos = pos + rng.uniform(-0.2, 0.2, size=pos.shape)
+    s = make_system(pos, 4, 6.0, 32, rng, name="full", eta=0.0, tau=10.0, seed=40)
+    w = brute.generalized_eigh_lapack(s.H, s.S)[0]
+    eta = w[-1] + 1.0
+    C0 = start_coefficients(s.S, s.M, 41)
+    _say(f"fully occupied N={s.N} M={s.M}")
+    solver, status = _run(lib_ok, s, C0, eta, math.inf, 1e-14, 5000)
+    E_ref = brute.closed_form_energy(w, s.M, eta)
+    assert abs(solver.energy() - E_ref) <= 1e-10 * abs(E_ref)
+    C = solver.get_C()
+    np.testing.assert_allclose(C.T @ C, np.linalg.inv(s.S), rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_graph_replay_matches_eager_launches(lib_ok, c2, precision, monkeypatch):
+    """Line searches replayed from the captured hipGraph give the eager trajectory bit for bit
+    (many replays, with host synchronizations between them)."""
+    s, C0, _ = c2
+    _say(f"graph vs eager {precision} c2")
+    traces = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("OMM_GRAPH", flag)
+        solver, _ = _run(lib_ok, s, C0, 0.5, 10.0, 0.0, 90, precision=precision, refine=True)
+        traces.append(solver.energy_trace())
+        solver.close()
+    assert len(traces[0]) == len(traces[1]) == 91
+    assert np.array_equal(traces[0], traces[1])
+    # the same in chunks: odd chunk lengths change the parity of the captured pair, and every
+    # call grows the trace buffer (its reallocation must drop the graph that points at it)
+    traces = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("OMM_GRAPH", flag)
+        solver, _ = _run(lib_ok, s, C0, 0.5, 10.0, 0.0, 7, precision=precision, refine=True)
+        for n in (13, 31, 39):
+            solver.iterate(n, 0.0)
+        traces.append(solver.energy_trace())
+        solver.close()
+    assert len(traces[0]) == len(traces[1]) == 91
+    assert np.array_equal(traces[0], traces[1])
+
+
 def test_error_paths(lib_ok, c1):
     from paper_1312_1549_amd import OMMError
 

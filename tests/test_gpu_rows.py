@@ -80,6 +80,10 @@ def test_autograd_backward_c5(torch, c5):
     Cstar = fd_solver.get_C()
     rng = np.random.default_rng(300)
     h = 1e-4
+    # Error of each directional derivative relative to the gradient's norm (Z has unit norm, so
+    # |<g, Z>| <= |g|): a direction nearly orthogonal to g has a tiny <g, Z>, and relative to that
+    # the finite-difference noise of two converged minima (~1e-12 |E| / 2h) is not small.
+    scale = {"H": float(np.linalg.norm(gH)), "S": float(np.linalg.norm(gS))}
     worst = 0.0
     for d in range(8):
         Z = rng.standard_normal((s.N, s.N))
@@ -96,9 +100,10 @@ def test_autograd_backward_c5(torch, c5):
                 Es.append(fd_solver.energy())
             fd = (Es[0] - Es[1]) / (2 * h)
             an = float(np.sum(g * Z))
-            worst = max(worst, abs(fd - an) / max(1e-6, abs(an)))
-    print(f"finite differences: worst rel err {worst:.2e}")
-    assert worst < 1e-4
+            print(f"  {which} direction {d}: fd {fd:.10e} analytic {an:.10e}")
+            worst = max(worst, abs(fd - an) / scale[which])
+    print(f"finite differences: worst error / |g| {worst:.2e}")
+    assert worst < 1e-6
 
 
 def test_batched_systems_match_closed_forms(torch):
