@@ -242,7 +242,7 @@ int tune_list(omm_batch* b, OpList& L) {
   BHIP(b, hipEventCreate(&e1));
   float best = 1e30f;
   int best_t = 0;
-  for (int t = 0; t < gemm_num_tiles(); ++t) {
+  for (int t = 0; t < gemm_grouped_num_tiles(); ++t) {
     BTRY(upload_list(b, L, t));
     BTRY(launch_list(b, L));
     BHIP(b, hipEventRecord(e0, b->stream));

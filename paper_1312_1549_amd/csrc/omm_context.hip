@@ -316,12 +316,25 @@ int autotune(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, int K, std::pair<int
 
 // One GEMM launch with a tuned (or heuristic) tiling. `tunable` is false for in-place updates,
 // which must not be run more than once.
+// OMM_TILE=<t> pins every GEMM that supports macro tile t to it (no split-K, no autotuning):
+// used to compare tile implementations against each other.
+int forced_tile() {
+  const char* e = getenv("OMM_TILE");
+  return (e && e[0]) ? atoi(e) : -1;
+}
+
 int gemm(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, const int* done, bool tunable = true) {
   const int K = ops[0].K[0] + (ops[0].nseg > 1 ? ops[0].K[1] : 0);
   const int M = ops[0].M, N = ops[0].N;
   heuristic_tiling(d, M, N, K);
   const double flops = 2.0 * M * N * (double)K * nops;
-  if (tunable && flops >= 2e9 && autotune_enabled()) {
+  const int ft = forced_tile();
+  GemmDesc df = d;
+  df.tile = ft;
+  df.splitk = 1;
+  if (ft >= 0 && gemm_supported(df)) {
+    d = df;
+  } else if (tunable && flops >= 2e9 && autotune_enabled()) {
     TuneKey key{{d.compute, d.ta, d.tb, d.tc, d.tx, d.la, d.lb, M, N, K, nops}};
     std::pair<int, int> choice{-1, 1};
     {

@@ -40,6 +40,26 @@ size_t gemm_splitk_ws_bytes(const GemmOp* ops, int nops, int splitk) {
 }
 
 int gemm_num_tiles() { return NTILES; }
+int gemm_grouped_num_tiles() { return NTILES_GROUPED; }
+
+namespace {
+// Preconditions of the direct-to-LDS tile: 16-byte aligned planes, leading dimensions that are
+// multiples of 8, and K-segment boundaries on 8-element boundaries.
+bool dma_ok(const GemmDesc& d, const GemmOp* ops, int nops) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  for (int i = 0; i < nops; ++i) {
+    const GemmOp& op = ops[i];
+    if (op.nseg == 2 && op.K[0] % 8 != 0) return false;
+    for (int g = 0; g < op.nseg; ++g) {
+      if (op.lda[g] % 8 != 0 || op.ldb[g] % 8 != 0) return false;
+      if (!al(op.A[g]) || !al(op.B[g])) return false;
+      if (d.compute != CBF16X2A && !al(op.Alo[g])) return false;
+      if (d.compute != CBF16X2B && !al(op.Blo[g])) return false;
+    }
+  }
+  return true;
+}
+}  // namespace
 
 bool gemm_supported(const GemmDesc& d) {
   if (d.tile < 0 || d.tile >= NTILES) return false;
@@ -75,11 +95,13 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
   const int M = ops[0].M, N = ops[0].N;
   if (M <= 0 || N <= 0) return hipSuccess;
   if (d.tile < 0 || d.tile >= NTILES) return hipErrorInvalidValue;
+  GemmDesc dd = d;
+  if (dd.tile == 5 && !dma_ok(dd, ops, nops)) dd.tile = 4;  // same 256 x 256 tile, register path
   gemm_fn fn = nullptr;
-  if (d.compute == CF64) fn = pick_f64(d);
-  else if (d.compute == CF32) fn = pick_f32(d);
-  else if (d.compute == CBF16X3) fn = pick_bf16x3(d);
-  else if (d.compute == CBF16X2A || d.compute == CBF16X2B) fn = pick_bf16x2(d);
+  if (dd.compute == CF64) fn = pick_f64(dd);
+  else if (dd.compute == CF32) fn = pick_f32(dd);
+  else if (dd.compute == CBF16X3) fn = pick_bf16x3(dd);
+  else if (dd.compute == CBF16X2A || dd.compute == CBF16X2B) fn = pick_bf16x2(dd);
   if (!fn) return hipErrorInvalidValue;
   const int bm = tile_bm(d.tile, d.compute), bn = tile_bn(d.tile, d.compute);
   const int tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);

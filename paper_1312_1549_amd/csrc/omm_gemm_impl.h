@@ -354,6 +354,34 @@ struct AccT<CF64> {
   typedef d4 type;
 };
 
+// Epilogue of one wave's TM x TN blocks at (r0, c0): C = alpha acc + beta X, or the FP64 split-K
+// partial at ws[(sp * nops + z) * M * N + ...].
+template <int MODE, typename TC, typename TX, int TM, int TN, typename acc_t>
+__device__ __forceinline__ void store_acc(const GemmOp& op, const acc_t (&acc)[TM][TN], int r0,
+                                          int c0, int lane, int sp, int nsplit, double* ws, int z,
+                                          int nops) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = MODE == CF64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        const int row = r0 + i * 16 + rr;
+        const int col = c0 + j * 16 + (lane & 15);
+        if (row < op.M && col < op.N) {
+          const double s = (double)acc[i][j][r];
+          if (nsplit > 1) {
+            ws[((int64_t)sp * nops + z) * op.M * op.N + (int64_t)row * op.N + col] = s;
+          } else {
+            double v = op.alpha * s;
+            if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
+            static_cast<TC*>(op.C)[(int64_t)row * op.ldc + col] = (TC)v;
+          }
+        }
+      }
+}
+
 // One output tile (tm, tn) of op, K split `sp` of `nsplit`. WM x WN waves, each wave TM x TN
 // blocks of 16 x 16; BK = K tile. Split-K partials go to ws[(sp * nops + z) * M * N + ...].
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB, int WM,
@@ -492,26 +520,162 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
     }
   }
 
+  store_acc<MODE, TC, TX, TM, TN>(op, acc, m0 + wm * TM * 16, n0 + wn * TN * 16, lane, sp, nsplit,
+                                  ws, z, nops);
+}
+
+// ---- direct-to-LDS pipeline: bf16 planes, A and B k-contiguous, 256 x 256 tile, 8 waves -----
+// Full K stages go from memory straight into LDS (global_load_lds_dwordx4: lane l of a wave
+// writes its 16 bytes at the wave's LDS base + 16 l), so no VGPRs hold staged tiles and no
+// ds_write is issued. NS stage buffers rotate: the loads of stage t + NS - 1 are issued right
+// after the barrier that opens stage t, which gives each load NS - 1 compute phases to land. The
+// rotated-chunk row layout of the register path is kept: LDS slot (row r, chunk l % 4) receives
+// logical chunk (l % 4 - l / 16) & 3 of row r. Rows past the matrix edge re-read the last row
+// (their outputs are never stored); a stage that runs past the end of K takes the register path
+// (zero fill). Requires 16-byte aligned plane pointers, leading dimensions that are multiples
+// of 8, and a first segment length that is a multiple of 8 (checked by the launcher).
+constexpr int DMA_BM = 256, DMA_BN = 256, DMA_BK = 32, DMA_PLANE = DMA_BM * DMA_BK;
+
+// s_waitcnt: vmcnt <= n, lgkmcnt = 0 (expcnt unconstrained)
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (0 << 8) | (((N >> 4) & 3) << 14));
+}
+
+template <int MODE, typename TC, typename TX, int NS>
+__device__ __forceinline__ void gemm_tile_dma(const GemmOp& op, int tm, int tn, int sp, int nsplit,
+                                              double* ws, int z, int nops) {
+  constexpr int WM = 2, WN = 4, TM = 8, TN = 4, NT = 512, BK = DMA_BK, RS = DMA_BK;
+  constexpr bool ONE_A = MODE == CBF16X2A, ONE_B = MODE == CBF16X2B;
+  constexpr int NBA = ONE_A ? 1 : 2, NBB = ONE_B ? 1 : 2, NPL = NBA + NBB;
+  constexpr int DPS = NPL * (DMA_BM * BK * 2 / 1024) / 8;  // 1 KB wave loads per wave per stage
+  static_assert(is_bf16_mode(MODE), "direct-to-LDS path: bf16 planes only");
+  static_assert(NS * NPL * DMA_PLANE * 2 <= 160 * 1024, "LDS budget");
+  typedef unsigned short lds_t;
+  typedef Stager<MODE, unsigned short, KC, DMA_BM, BK, NT, true, ONE_A> SA;
+  typedef Stager<MODE, unsigned short, KC, DMA_BN, BK, NT, true, ONE_B> SB;
+
+  __shared__ __attribute__((aligned(16))) lds_t L[NS * NPL * DMA_PLANE];
+
+  const int m0 = tm * DMA_BM, n0 = tn * DMA_BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  f4 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+  // this lane's row within a 16-row wave chunk, and the logical 8-element chunk it fetches
+  const int lrow = lane >> 2, lchunk = ((lane & 3) - (lane >> 4)) & 3;
+
+  for (int seg = 0; seg < op.nseg; ++seg) {
+    int kb, ke;
+    split_range<BK>(op, seg, sp, nsplit, kb, ke);
+    if (kb >= ke) continue;
+    const unsigned short* plane[4];
+    int64_t ldp[4];
+    int row0[4], rmax[4];
+    {
+      int p = 0;
+      plane[p] = static_cast<const unsigned short*>(op.A[seg]);
+      ldp[p] = op.lda[seg]; row0[p] = m0; rmax[p] = op.M; ++p;
+      if constexpr (!ONE_A) {
+        plane[p] = static_cast<const unsigned short*>(op.Alo[seg]);
+        ldp[p] = op.lda[seg]; row0[p] = m0; rmax[p] = op.M; ++p;
+      }
+      plane[p] = static_cast<const unsigned short*>(op.B[seg]);
+      ldp[p] = op.ldb[seg]; row0[p] = n0; rmax[p] = op.N; ++p;
+      if constexpr (!ONE_B) {
+        plane[p] = static_cast<const unsigned short*>(op.Blo[seg]);
+        ldp[p] = op.ldb[seg]; row0[p] = n0; rmax[p] = op.N; ++p;
+      }
+    }
+    // per-lane source of each of this wave's DPS wave loads (k offset added per stage)
+    const unsigned short* src[DPS];
+    int dst[DPS];  // LDS element offset within a stage buffer (wave-uniform)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rr = MODE == CF64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
-        const int row = m0 + wm * TM * 16 + i * 16 + rr;
-        const int col = n0 + wn * TN * 16 + j * 16 + (lane & 15);
-        if (row < op.M && col < op.N) {
-          const double s = (double)acc[i][j][r];
-          if (nsplit > 1) {
-            ws[((int64_t)sp * nops + z) * op.M * op.N + (int64_t)row * op.N + col] = s;
-          } else {
-            double v = op.alpha * s;
-            if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
-            static_cast<TC*>(op.C)[(int64_t)row * op.ldc + col] = (TC)v;
-          }
+    for (int i = 0; i < DPS; ++i) {
+      const int q = wave + 8 * i;  // wave chunk: plane q / 16, rows 16 (q % 16) ..
+      const int pl = q / 16, j = q % 16;
+      const int gr = min(row0[pl] + 16 * j + lrow, rmax[pl] - 1);
+      src[i] = plane[pl] + (int64_t)gr * ldp[pl] + 8 * lchunk;
+      dst[i] = pl * DMA_PLANE + 512 * j;
+    }
+    const int nst = (ke - kb + BK - 1) / BK;
+    auto full = [&](int st) { return kb + (st + 1) * BK <= ke; };
+    auto issue = [&](int st) {
+      lds_t* buf = L + (st % NS) * NPL * DMA_PLANE;
+      const int k0 = kb + st * BK;
+      if (full(st)) {
+#pragma unroll
+        for (int i = 0; i < DPS; ++i)
+          __builtin_amdgcn_global_load_lds(src[i] + k0, buf + dst[i], 16, 0, 0);
+      } else {
+        SA sa;
+        SB sb;
+        sa.load(op.A[seg], op.Alo[seg], op.lda[seg], m0, op.M, k0, ke, tid, true);
+        sb.load(op.B[seg], op.Blo[seg], op.ldb[seg], n0, op.N, k0, ke, tid, true);
+        sa.store(buf, buf + (NBA - 1) * DMA_PLANE, tid);
+        sb.store(buf + NBA * DMA_PLANE, buf + (NPL - 1) * DMA_PLANE, tid);
+      }
+    };
+    __syncthreads();  // the previous segment's readers are done with every buffer
+#pragma unroll
+    for (int st = 0; st < NS - 1; ++st)
+      if (st < nst) issue(st);
+    for (int t = 0; t < nst; ++t) {
+      // this wave's loads of stage t have landed (those of stage t + 1 may still be in flight),
+      // then every wave's have
+      if (NS > 2 && t + 1 < nst && full(t + 1)) wait_vm_lgkm0<(NS > 2 ? DPS : 0)>();
+      else wait_vm_lgkm0<0>();
+      __builtin_amdgcn_s_barrier();
+      if (t + NS - 1 < nst) issue(t + NS - 1);
+      const lds_t* buf = L + (t % NS) * NPL * DMA_PLANE;
+      const lds_t* a0 = buf;
+      const lds_t* a1 = buf + (NBA - 1) * DMA_PLANE;
+      const lds_t* b0 = buf + NBA * DMA_PLANE;
+      const lds_t* b1 = buf + (NPL - 1) * DMA_PLANE;
+      const int kof = 8 * (lane >> 4);
+      auto frag = [&](const lds_t* base, int r) {
+        return __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(
+                                           base + lds_off<true, RS>(r, kof)));
+      };
+      bf8 bh[TN], bl[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int r = wn * TN * 16 + j * 16 + (lane & 15);
+        bh[j] = frag(b0, r);
+        bl[j] = ONE_B ? bh[j] : frag(b1, r);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = wm * TM * 16 + i * 16 + (lane & 15);
+        const bf8 ah = frag(a0, r), al = ONE_A ? ah : frag(a1, r);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          if constexpr (!ONE_A)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+          if constexpr (!ONE_B)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
         }
       }
+    }
+  }
+  store_acc<MODE, TC, TX, TM, TN>(op, acc, m0 + wm * TM * 16, n0 + wn * TN * 16, lane, sp, nsplit,
+                                  ws, z, nops);
+}
+
+template <int MODE, typename TC, typename TX, int NS>
+__global__ __launch_bounds__(512, 1) void gemm_kernel_dma(GemmBatch batch, const int* done,
+                                                          int nsplit, double* ws) {
+  if (done && *done) return;
+  const GemmOp& op = batch.op[blockIdx.z];
+  const int tiles_m = (op.M + DMA_BM - 1) / DMA_BM, tiles_n = (op.N + DMA_BN - 1) / DMA_BN;
+  int tm, tn;
+  if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
+  gemm_tile_dma<MODE, TC, TX, NS>(op, tm, tn, blockIdx.y, nsplit, ws, blockIdx.z, gridDim.z);
 }
 
 // Up to 4 same-shape products (blockIdx.z), XCD-remapped tiles (blockIdx.x), split-K (y).
@@ -564,16 +728,20 @@ typedef void (*grouped_fn)(GroupedArgs);
 
 // Tile shapes (macro tile M x N): 0: 128x128 (4 waves), 1: 64x64 (4 waves, 2 workgroups per
 // CU), 2: 256x128 (8 waves), 3: 128x256 (8 waves), 4: BF16x3: 256x256 (8 waves of 128x64,
-// swizzled unpadded LDS); FP64/FP32: 128x128 with 2 workgroups per CU.
-constexpr int NTILES = 5;
+// swizzled unpadded LDS); FP64/FP32: 128x128 with 2 workgroups per CU. 5: BF16 modes on planes
+// with both operands k-contiguous: the 256x256 tile fed by direct-to-LDS loads (3 stages for the
+// two-product modes, 2 for BF16x3).
+constexpr int NTILES = 6;
+constexpr int NTILES_GROUPED = 5;
+inline bool tile_big(int t, int mode) { return (t == 4 || t == 5) && is_bf16_mode(mode); }
 inline int tile_bm(int t, int mode) {
-  return t == 1 ? 64 : (t == 2 || (t == 4 && is_bf16_mode(mode)) ? 256 : 128);
+  return t == 1 ? 64 : (t == 2 || tile_big(t, mode) ? 256 : 128);
 }
 inline int tile_bn(int t, int mode) {
-  return t == 1 ? 64 : (t == 3 || (t == 4 && is_bf16_mode(mode)) ? 256 : 128);
+  return t == 1 ? 64 : (t == 3 || tile_big(t, mode) ? 256 : 128);
 }
 inline int tile_threads(int t, int mode) {
-  return (t == 2 || t == 3 || (t == 4 && is_bf16_mode(mode))) ? 512 : 256;
+  return (t == 2 || t == 3 || tile_big(t, mode)) ? 512 : 256;
 }
 
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB>
@@ -606,6 +774,12 @@ gemm_fn pick_tile(int tile) {
         return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 4, 8, 4, BK, 1, true>;
       else
         return gemm_kernel<MODE, TA, TB, TC, TX, LA, LB, 2, 2, 4, 4, BK, 2>;
+    case 5:
+      if constexpr (is_bf16_mode(MODE) && std::is_same<TA, unsigned short>::value &&
+                    std::is_same<TB, unsigned short>::value && LA == KC && LB == KC)
+        return gemm_kernel_dma<MODE, TC, TX, MODE == CBF16X3 ? 2 : 3>;
+      else
+        return nullptr;
     default: return nullptr;
   }
 }

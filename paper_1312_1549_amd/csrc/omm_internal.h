@@ -67,6 +67,7 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
                        double* ws, size_t ws_bytes, hipStream_t s);
 size_t gemm_splitk_ws_bytes(const GemmOp* ops, int nops, int splitk);
 int gemm_num_tiles();
+int gemm_grouped_num_tiles();
 bool gemm_supported(const GemmDesc& d);
 int gemm_tile_rows(int tile, int mode);
 int gemm_tile_cols(int tile, int mode);

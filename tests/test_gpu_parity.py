@@ -201,6 +201,30 @@ def test_odd_sizes_take_the_unvectorized_paths(lib_ok, precision):
         np.testing.assert_allclose(solver.energy_trace()[:21], ref.energies[:21], rtol=1e-10)
 
 
+@pytest.mark.parametrize("M", [37, 40])
+@pytest.mark.parametrize("refine", [True, False])
+def test_direct_to_lds_tile_matches_register_tile(lib_ok, M, refine, monkeypatch):
+    """The 256 x 256 BF16 tile fed by direct-to-LDS loads (tile 5) sums the same products in the
+    same order as the register-staged tile (tile 4): trajectories agree bit for bit. N = 200
+    leaves a partial K stage and partial row tiles; M = 40 also takes the gradient (two K
+    segments) through the direct loads, M = 37 makes it fall back to the register path."""
+    rng = np.random.default_rng(50 + M)
+    pos = lattice_positions((5, 5, 2), 2.5)
+    pos = pos + rng.uniform(-0.2, 0.2, size=pos.shape)
+    s = make_system(pos, 4, 6.0, M, rng, name="dma", eta=0.5, tau=10.0, seed=50 + M)
+    C0 = start_coefficients(s.S, s.M, 51)
+    _say(f"tile 5 vs tile 4 N={s.N} M={s.M} refine={refine}")
+    traces = []
+    for tile in ("4", "5"):
+        monkeypatch.setenv("OMM_TILE", tile)
+        solver, _ = _run(lib_ok, s, C0, 0.5, 10.0, 0.0, 30, precision="bf16x3", refine=refine)
+        traces.append(solver.energy_trace())
+        solver.close()
+    assert len(traces[0]) == 31
+    assert np.array_equal(traces[0], traces[1])
+    assert traces[1][-1] < traces[1][0]
+
+
 def test_fully_occupied_limit(lib_ok):
     """M = N: every eigenvector is occupied; with eta above the whole spectrum the minimum is
     2 sum_i (eps_i - eta) and SW = I (C^T C = S^-1 in row form)."""
