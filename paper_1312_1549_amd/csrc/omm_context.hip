@@ -259,9 +259,9 @@ void tune_save_locked() {
 
 void drop_graph(omm_ctx* c);
 
-int ensure_ws(omm_ctx* c, const GemmOp* ops, int nops, int splitk) {
-  if (splitk <= 1) return OMM_OK;
-  const size_t need = gemm_splitk_ws_bytes(ops, nops, splitk);
+int ensure_ws(omm_ctx* c, const GemmDesc& d, const GemmOp* ops, int nops) {
+  const size_t need = gemm_ws_bytes(d, ops, nops);
+  if (need == 0) return OMM_OK;
   if (need > c->ws_bytes) {
     drop_graph(c);  // a captured graph holds the old workspace address
     dfree(c->ws);
@@ -284,8 +284,11 @@ int autotune(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, int K, std::pair<int
     const int bm = gemm_tile_rows(t, d.compute), bn = gemm_tile_cols(t, d.compute);
     const long tiles = (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
     if (tiles >= 32 || t == 1) cands.push_back({t, 1});
-    for (int sk : {2, 4, 8, 16})
-      if (tiles * sk <= 4096 && tiles < 512 && K / sk >= 256) cands.push_back({t, sk});
+    for (int sk : {2, 4, 8, 16}) {
+      dt.splitk = sk;
+      if (gemm_supported(dt) && tiles * sk <= 4096 && tiles < 512 && K / sk >= 256)
+        cands.push_back({t, sk});
+    }
   }
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
@@ -296,7 +299,7 @@ int autotune(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, int K, std::pair<int
     GemmDesc dt = d;
     dt.tile = cand.first;
     dt.splitk = cand.second;
-    TRY(ensure_ws(c, ops, nops, dt.splitk));
+    TRY(ensure_ws(c, dt, ops, nops));
     HIPCHK(c, gemm_launch(dt, ops, nops, nullptr, c->ws, c->ws_bytes, c->stream));
     HIPCHK(c, hipEventRecord(e0, c->stream));
     HIPCHK(c, gemm_launch(dt, ops, nops, nullptr, c->ws, c->ws_bytes, c->stream));
@@ -356,7 +359,7 @@ int gemm(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, const int* done, bool tu
       d.splitk = choice.second;
     }
   }
-  TRY(ensure_ws(c, ops, nops, d.splitk));
+  TRY(ensure_ws(c, d, ops, nops));
   HIPCHK(c, gemm_launch(d, ops, nops, done, c->ws, c->ws_bytes, c->stream));
   return OMM_OK;
 }

@@ -9,6 +9,8 @@ gemm_fn pick_f64(const GemmDesc& d);
 gemm_fn pick_f32(const GemmDesc& d);
 gemm_fn pick_bf16x3(const GemmDesc& d);
 gemm_fn pick_bf16x2(const GemmDesc& d);
+sk_fn pick_sk_bf16x3(const GemmDesc& d);
+sk_fn pick_sk_bf16x2(const GemmDesc& d);
 grouped_fn pick_grouped_f32(const GemmDesc& d);
 
 namespace {
@@ -39,6 +41,11 @@ size_t gemm_splitk_ws_bytes(const GemmOp* ops, int nops, int splitk) {
   return (size_t)splitk * nops * (size_t)ops[0].M * ops[0].N * sizeof(double);
 }
 
+size_t gemm_ws_bytes(const GemmDesc& d, const GemmOp* ops, int nops) {
+  if (d.tile == 6) return (size_t)2 * SK_GRID * DMA_BM * DMA_BN * sizeof(float);
+  return gemm_splitk_ws_bytes(ops, nops, d.splitk);
+}
+
 int gemm_num_tiles() { return NTILES; }
 int gemm_grouped_num_tiles() { return NTILES_GROUPED; }
 
@@ -61,8 +68,17 @@ bool dma_ok(const GemmDesc& d, const GemmOp* ops, int nops) {
 }
 }  // namespace
 
+namespace {
+sk_fn pick_sk(const GemmDesc& d) {
+  if (d.compute == CBF16X3) return pick_sk_bf16x3(d);
+  if (d.compute == CBF16X2A || d.compute == CBF16X2B) return pick_sk_bf16x2(d);
+  return nullptr;
+}
+}  // namespace
+
 bool gemm_supported(const GemmDesc& d) {
   if (d.tile < 0 || d.tile >= NTILES) return false;
+  if (d.tile == 6) return d.splitk <= 1 && pick_sk(d) != nullptr;
   if (d.compute == CF64) return pick_f64(d) != nullptr;
   if (d.compute == CF32) return pick_f32(d) != nullptr;
   if (d.compute == CBF16X3) return pick_bf16x3(d) != nullptr;
@@ -96,6 +112,35 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
   if (M <= 0 || N <= 0) return hipSuccess;
   if (d.tile < 0 || d.tile >= NTILES) return hipErrorInvalidValue;
   GemmDesc dd = d;
+  if (dd.tile == 6) {
+    if (dma_ok(dd, ops, nops)) {
+      sk_fn fn = pick_sk(dd);
+      if (!fn || dd.splitk > 1) return hipErrorInvalidValue;
+      if (!ws || ws_bytes < gemm_ws_bytes(dd, ops, nops)) return hipErrorInvalidValue;
+      const int tiles = ((M + DMA_BM - 1) / DMA_BM) * ((N + DMA_BN - 1) / DMA_BN);
+      const int ktot = ops[0].K[0] + (ops[0].nseg > 1 ? ops[0].K[1] : 0);
+      for (int i = 1; i < nops; ++i)
+        if (ops[i].nseg != ops[0].nseg || ops[i].K[0] != ops[0].K[0] ||
+            (ops[0].nseg > 1 && ops[i].K[1] != ops[0].K[1]))
+          return hipErrorInvalidValue;  // one K schedule for every product of the launch
+      SkArgs a;
+      a.T = tiles * nops;
+      a.nk = (ktot + DMA_BK - 1) / DMA_BK;
+      a.R = a.T / SK_GRID;
+      a.W = (int64_t)(a.T - a.R * SK_GRID) * a.nk;
+      float* parts = reinterpret_cast<float*>(ws);
+      hipLaunchKernelGGL(fn, dim3(SK_GRID), dim3(512), 0, s, b, done, a, parts);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess || a.W == 0) return e;
+      sk_fixup_fn fx = dd.tc == T_F64 ? gemm_sk_fixup<double, double> : gemm_sk_fixup<float, float>;
+      if ((dd.tc == T_F64) != (dd.tx == T_F64)) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(fx, dim3(a.T - a.R * SK_GRID), dim3(512), 0, s, b, done, a, SK_GRID,
+                         (const float*)parts);
+      return hipGetLastError();
+    }
+    dd.tile = 4;  // same 256 x 256 tile on the register path, one workgroup per tile
+    dd.splitk = 1;
+  }
   if (dd.tile == 5 && !dma_ok(dd, ops, nops)) dd.tile = 4;  // same 256 x 256 tile, register path
   gemm_fn fn = nullptr;
   if (dd.compute == CF64) fn = pick_f64(dd);
@@ -103,14 +148,14 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
   else if (dd.compute == CBF16X3) fn = pick_bf16x3(dd);
   else if (dd.compute == CBF16X2A || dd.compute == CBF16X2B) fn = pick_bf16x2(dd);
   if (!fn) return hipErrorInvalidValue;
-  const int bm = tile_bm(d.tile, d.compute), bn = tile_bn(d.tile, d.compute);
+  const int bm = tile_bm(dd.tile, dd.compute), bn = tile_bn(dd.tile, dd.compute);
   const int tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
   const int per = (tiles + 7) / 8;
-  const int splitk = d.splitk > 1 ? d.splitk : 1;
+  const int splitk = dd.splitk > 1 ? dd.splitk : 1;
   if (splitk > 1 && (!ws || ws_bytes < gemm_splitk_ws_bytes(ops, nops, splitk)))
     return hipErrorInvalidValue;
   dim3 grid(8 * per, splitk, nops);
-  hipLaunchKernelGGL(fn, grid, dim3(tile_threads(d.tile, d.compute)), 0, s, b, done, splitk, ws);
+  hipLaunchKernelGGL(fn, grid, dim3(tile_threads(dd.tile, dd.compute)), 0, s, b, done, splitk, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splitk == 1) return e;
   const int64_t mn = (int64_t)M * N;
@@ -118,8 +163,8 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
   if (blocks > 4096) blocks = 4096;
   dim3 rgrid(blocks, nops);
   void (*red)(GemmBatch, const int*, int, const double*) = nullptr;
-  if (d.tc == T_F64) red = d.tx == T_F64 ? splitk_reduce<double, double> : splitk_reduce<double, float>;
-  else red = d.tx == T_F64 ? splitk_reduce<float, double> : splitk_reduce<float, float>;
+  if (dd.tc == T_F64) red = dd.tx == T_F64 ? splitk_reduce<double, double> : splitk_reduce<double, float>;
+  else red = dd.tx == T_F64 ? splitk_reduce<float, double> : splitk_reduce<float, float>;
   hipLaunchKernelGGL(red, rgrid, dim3(256), 0, s, b, done, splitk, (const double*)ws);
   return hipGetLastError();
 }

@@ -23,5 +23,21 @@ gemm_fn pick_bf16x2(const GemmDesc& d) {
   return nullptr;
 }
 
+namespace {
+template <int MODE>
+sk_fn pick_sk_mode(const GemmDesc& d) {
+  if (d.la != KC || d.lb != KC || d.ta != T_BF16P || d.tb != T_BF16P) return nullptr;
+  if (d.tc == T_F32 && d.tx == T_F32) return pick_sk_kernel<MODE, float, float>();
+  if (d.tc == T_F64 && d.tx == T_F64) return pick_sk_kernel<MODE, double, double>();
+  return nullptr;
+}
+}  // namespace
+
+sk_fn pick_sk_bf16x2(const GemmDesc& d) {
+  if (d.compute == CBF16X2A) return pick_sk_mode<CBF16X2A>(d);
+  if (d.compute == CBF16X2B) return pick_sk_mode<CBF16X2B>(d);
+  return nullptr;
+}
+
 }  // namespace gemm_detail
 }  // namespace omm

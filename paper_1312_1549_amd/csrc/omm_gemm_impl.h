@@ -89,6 +89,14 @@ __device__ __forceinline__ void split_range(const GemmOp& op, int seg, int sp, i
   ke = min(g1 - off, op.K[seg]);
 }
 
+// The part [g0, g1) of the concatenated K of all segments that falls in segment `seg`.
+__device__ __forceinline__ void seg_range(const GemmOp& op, int seg, int g0, int g1, int& kb,
+                                          int& ke) {
+  const int off = seg == 0 ? 0 : op.K[0];
+  kb = max(g0 - off, 0);
+  ke = min(g1 - off, op.K[seg]);
+}
+
 // Per-mode element types: LDS element, register staging element, vector width of KC loads.
 template <int MODE>
 struct ModeTraits;
@@ -542,10 +550,17 @@ __device__ __forceinline__ void wait_vm_lgkm0() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (0 << 8) | (((N >> 4) & 3) << 14));
 }
 
-template <int MODE, typename TC, typename TX, int NS>
-__device__ __forceinline__ void gemm_tile_dma(const GemmOp& op, int tm, int tn, int sp, int nsplit,
-                                              double* ws, int z, int nops) {
-  constexpr int WM = 2, WN = 4, TM = 8, TN = 4, NT = 512, BK = DMA_BK, RS = DMA_BK;
+constexpr int DMA_TM = 8, DMA_TN = 4;  // 16 x 16 blocks per wave (wave grid 2 x 4)
+template <int KIND, typename TC>
+struct DmaUser {};
+
+// Accumulates the K range [g0, g1) (concatenated over the segments) of tile (tm, tn) into acc.
+// USER (the calling kernel and its output type) only makes each kernel instantiate its own copy:
+// the host pass of hipcc rejects one such device template shared by two kernels.
+template <int MODE, int NS, typename USER>
+__device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int tn, int g0, int g1,
+                                                  f4 (&acc)[DMA_TM][DMA_TN]) {
+  constexpr int WM = 2, TM = DMA_TM, TN = DMA_TN, NT = 512, BK = DMA_BK, RS = DMA_BK;
   constexpr bool ONE_A = MODE == CBF16X2A, ONE_B = MODE == CBF16X2B;
   constexpr int NBA = ONE_A ? 1 : 2, NBB = ONE_B ? 1 : 2, NPL = NBA + NBB;
   constexpr int DPS = NPL * (DMA_BM * BK * 2 / 1024) / 8;  // 1 KB wave loads per wave per stage
@@ -560,7 +575,6 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmOp& op, int tm, int tn, 
   const int m0 = tm * DMA_BM, n0 = tn * DMA_BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
-  f4 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -571,7 +585,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmOp& op, int tm, int tn, 
 
   for (int seg = 0; seg < op.nseg; ++seg) {
     int kb, ke;
-    split_range<BK>(op, seg, sp, nsplit, kb, ke);
+    seg_range(op, seg, g0, g1, kb, ke);
     if (kb >= ke) continue;
     const unsigned short* plane[4];
     int64_t ldp[4];
@@ -663,8 +677,6 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmOp& op, int tm, int tn, 
       }
     }
   }
-  store_acc<MODE, TC, TX, TM, TN>(op, acc, m0 + wm * TM * 16, n0 + wn * TN * 16, lane, sp, nsplit,
-                                  ws, z, nops);
 }
 
 template <int MODE, typename TC, typename TX, int NS>
@@ -675,7 +687,133 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_dma(GemmBatch batch, const
   const int tiles_m = (op.M + DMA_BM - 1) / DMA_BM, tiles_n = (op.N + DMA_BN - 1) / DMA_BN;
   int tm, tn;
   if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
-  gemm_tile_dma<MODE, TC, TX, NS>(op, tm, tn, blockIdx.y, nsplit, ws, blockIdx.z, gridDim.z);
+  const int ktot = op.K[0] + (op.nseg > 1 ? op.K[1] : 0);
+  const int nk = (ktot + DMA_BK - 1) / DMA_BK;
+  const int per = (nk + nsplit - 1) / nsplit;
+  const int sp = blockIdx.y;
+  f4 acc[DMA_TM][DMA_TN];
+  gemm_tile_dma_acc<MODE, NS, DmaUser<0, TC>>(op, tm, tn, sp * per * DMA_BK,
+                                              min(ktot, (sp + 1) * per * DMA_BK), acc);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  store_acc<MODE, TC, TX, DMA_TM, DMA_TN>(op, acc, tm * DMA_BM + (wave % 2) * DMA_TM * 16,
+                                          tn * DMA_BN + (wave / 2) * DMA_TN * 16, lane, sp, nsplit,
+                                          ws, blockIdx.z, gridDim.z);
+}
+
+// ---- stream-K schedule of the direct-to-LDS tile --------------------------------------------
+// T tile-ops (tiles x products, M-fastest within a product) of nk K steps each run on G
+// persistent workgroups (G a multiple of 8, one per CU). Rounds r < R = T / G are data
+// parallel: workgroup g takes tile-op r G + h(g), where h(g) = (g % 8) (G / 8) + g / 8 keeps 32
+// consecutive tile-ops (4 column panels x 8 row tiles sharing operand panels) on one XCD. The
+// last T - R G tile-ops (W = (T - R G) nk steps) are cut evenly: workgroup h(g) takes steps
+// [h W / G, (h + 1) W / G), at most two tile parts since W / G < nk. A part that is not a whole
+// tile leaves its FP32 accumulators in workspace slot 2 h (the first part of h's range) or
+// 2 h + 1 (the second); gemm_sk_fixup sums the parts of each cut tile in K order.
+struct SkArgs {
+  int T;       // tile-ops
+  int nk;      // K steps per tile
+  int R;       // data-parallel rounds
+  int64_t W;   // K steps of the cut tile-ops
+};
+
+__device__ __forceinline__ int64_t sk_bound(int64_t W, int h, int G) { return W * h / G; }
+
+template <int MODE, typename TC, typename TX, int NS>
+__global__ __launch_bounds__(512, 1) void gemm_kernel_sk(GemmBatch batch, const int* done, SkArgs a,
+                                                         float* parts) {
+  if (done && *done) return;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int h = (g & 7) * (G >> 3) + (g >> 3);
+  const GemmOp& op0 = batch.op[0];
+  const int tiles_m = (op0.M + DMA_BM - 1) / DMA_BM, tiles_n = (op0.N + DMA_BN - 1) / DMA_BN;
+  const int per_op = tiles_m * tiles_n;
+  const int ktot = op0.K[0] + (op0.nseg > 1 ? op0.K[1] : 0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  f4 acc[DMA_TM][DMA_TN];
+  auto locate = [&](int to, const GemmOp*& op, int& tm, int& tn) {
+    const int z = to / per_op, t = to % per_op;
+    op = &batch.op[z];
+    tm = t % tiles_m;
+    tn = t / tiles_m;
+  };
+  // data-parallel rounds: whole tiles
+  for (int r = 0; r < a.R; ++r) {
+    const GemmOp* op;
+    int tm, tn;
+    locate(r * G + h, op, tm, tn);
+    gemm_tile_dma_acc<MODE, NS, DmaUser<1, TC>>(*op, tm, tn, 0, ktot, acc);
+    store_acc<MODE, TC, TX, DMA_TM, DMA_TN>(*op, acc, tm * DMA_BM + (wave % 2) * DMA_TM * 16,
+                                            tn * DMA_BN + (wave / 2) * DMA_TN * 16, lane, 0, 1,
+                                            nullptr, 0, 1);
+  }
+  // cut tiles: this workgroup's share of the remaining K steps
+  const int64_t u0 = sk_bound(a.W, h, G), u1 = sk_bound(a.W, h + 1, G);
+  int part = 0;
+  for (int64_t u = u0; u < u1; ++part) {
+    const int q = (int)(u / a.nk);  // cut tile index
+    const int k0 = (int)(u - (int64_t)q * a.nk);
+    const int k1 = (int)min((int64_t)a.nk, k0 + (u1 - u));
+    const GemmOp* op;
+    int tm, tn;
+    locate(a.R * G + q, op, tm, tn);
+    gemm_tile_dma_acc<MODE, NS, DmaUser<1, TC>>(*op, tm, tn, k0 * DMA_BK, min(ktot, k1 * DMA_BK),
+                                                acc);
+    if (k0 == 0 && k1 == a.nk) {
+      store_acc<MODE, TC, TX, DMA_TM, DMA_TN>(*op, acc, tm * DMA_BM + (wave % 2) * DMA_TM * 16,
+                                              tn * DMA_BN + (wave / 2) * DMA_TN * 16, lane, 0, 1,
+                                              nullptr, 0, 1);
+    } else {
+      float* slot = parts + (int64_t)(2 * h + part) * (DMA_BM * DMA_BN);
+#pragma unroll
+      for (int i = 0; i < DMA_TM; ++i)
+#pragma unroll
+        for (int j = 0; j < DMA_TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            slot[((i * DMA_TN + j) * 4 + r) * 512 + threadIdx.x] = acc[i][j][r];
+    }
+    u += k1 - k0;
+  }
+}
+
+// Sums the parts of cut tile blockIdx.x in K order (FP64) and applies the epilogue. Parts and
+// the element each thread owns follow the layout gemm_kernel_sk writes.
+template <typename TC, typename TX>
+__global__ __launch_bounds__(512) void gemm_sk_fixup(GemmBatch batch, const int* done, SkArgs a,
+                                                     int G, const float* parts) {
+  if (done && *done) return;
+  const int q = blockIdx.x;
+  const GemmOp& op0 = batch.op[0];
+  const int tiles_m = (op0.M + DMA_BM - 1) / DMA_BM, tiles_n = (op0.N + DMA_BN - 1) / DMA_BN;
+  const int per_op = tiles_m * tiles_n;
+  const int to = a.R * G + q, z = to / per_op, t = to % per_op;
+  const GemmOp& op = batch.op[z];
+  const int tm = t % tiles_m, tn = t / tiles_m;
+  const int64_t s0 = (int64_t)q * a.nk, s1 = s0 + a.nk;
+  // workgroups (in schedule order h) whose share meets [s0, s1)
+  int hA = (int)((s0 * G) / a.W);
+  while (hA > 0 && sk_bound(a.W, hA, G) > s0) --hA;
+  while (sk_bound(a.W, hA + 1, G) <= s0) ++hA;
+  if (sk_bound(a.W, hA + 1, G) >= s1) return;  // one workgroup had the whole tile and stored it
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = tm * DMA_BM + (wave % 2) * DMA_TM * 16, c0 = tn * DMA_BN + (wave / 2) * DMA_TN * 16;
+  for (int e = 0; e < DMA_TM * DMA_TN * 4; ++e) {
+    double sum = 0.0;
+    for (int hh = hA; hh < G && sk_bound(a.W, hh, G) < s1; ++hh) {
+      const int64_t b = sk_bound(a.W, hh, G);
+      if (sk_bound(a.W, hh + 1, G) <= b) continue;  // empty share
+      const int slot = 2 * hh + (b < s0 ? 1 : 0);
+      sum += (double)parts[(int64_t)slot * (DMA_BM * DMA_BN) + e * 512 + threadIdx.x];
+    }
+    const int i = e / (DMA_TN * 4), j = (e / 4) % DMA_TN, r = e % 4;
+    const int row = r0 + i * 16 + 4 * (lane >> 4) + r;
+    const int col = c0 + j * 16 + (lane & 15);
+    if (row < op.M && col < op.N) {
+      double v = op.alpha * sum;
+      if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
+      static_cast<TC*>(op.C)[(int64_t)row * op.ldc + col] = (TC)v;
+    }
+  }
 }
 
 // Up to 4 same-shape products (blockIdx.z), XCD-remapped tiles (blockIdx.x), split-K (y).
@@ -725,15 +863,25 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_grouped_kernel(Grouped
 }
 
 typedef void (*grouped_fn)(GroupedArgs);
+typedef void (*sk_fn)(GemmBatch, const int*, SkArgs, float*);
+typedef void (*sk_fixup_fn)(GemmBatch, const int*, SkArgs, int, const float*);
+
+template <int MODE, typename TC, typename TX>
+sk_fn pick_sk_kernel() {
+  return gemm_kernel_sk<MODE, TC, TX, MODE == CBF16X3 ? 2 : 3>;
+}
 
 // Tile shapes (macro tile M x N): 0: 128x128 (4 waves), 1: 64x64 (4 waves, 2 workgroups per
 // CU), 2: 256x128 (8 waves), 3: 128x256 (8 waves), 4: BF16x3: 256x256 (8 waves of 128x64,
 // swizzled unpadded LDS); FP64/FP32: 128x128 with 2 workgroups per CU. 5: BF16 modes on planes
 // with both operands k-contiguous: the 256x256 tile fed by direct-to-LDS loads (3 stages for the
 // two-product modes, 2 for BF16x3).
-constexpr int NTILES = 6;
+//    6: tile 5 on a stream-K schedule (persistent, whole-tile rounds, then the remaining tiles
+//       cut evenly across the workgroups).
+constexpr int NTILES = 7;
 constexpr int NTILES_GROUPED = 5;
-inline bool tile_big(int t, int mode) { return (t == 4 || t == 5) && is_bf16_mode(mode); }
+constexpr int SK_GRID = 256;  // one workgroup per CU
+inline bool tile_big(int t, int mode) { return t >= 4 && is_bf16_mode(mode); }
 inline int tile_bm(int t, int mode) {
   return t == 1 ? 64 : (t == 2 || tile_big(t, mode) ? 256 : 128);
 }

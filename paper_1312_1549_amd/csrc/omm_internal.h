@@ -57,7 +57,7 @@ struct GemmDesc {
   int compute;         // Compute
   int ta, tb, tc, tx;  // ElemType of A, B, C, X
   int la, lb;          // Layout of A, B
-  int tile;            // macro tile, see gemm_tile_rows / gemm_tile_cols (0..4)
+  int tile;            // macro tile, see gemm_tile_rows / gemm_tile_cols (0..6)
   int splitk;          // >1: K split across workgroups, partials reduced in FP64 (needs ws)
 };
 
@@ -66,6 +66,8 @@ struct GemmDesc {
 hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int* done,
                        double* ws, size_t ws_bytes, hipStream_t s);
 size_t gemm_splitk_ws_bytes(const GemmOp* ops, int nops, int splitk);
+// Workspace a launch with descriptor d needs (split-K partials, or stream-K tile parts).
+size_t gemm_ws_bytes(const GemmDesc& d, const GemmOp* ops, int nops);
 int gemm_num_tiles();
 int gemm_grouped_num_tiles();
 bool gemm_supported(const GemmDesc& d);
