@@ -241,7 +241,7 @@ def main():
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=80)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
@@ -249,7 +249,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison rate")
     ap.add_argument("--max-iter", type=int, default=4000)
-    ap.add_argument("--resync", type=int, default=40)
+    ap.add_argument("--resync", type=int, default=80)
     ap.add_argument("--cpu-iters", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -74,7 +74,7 @@ int omm_set_precision(omm_ctx *ctx, int mode, int fp64_refine);
 /* Stopping threshold of the FP32 phase of OMM_FP32 + refinement (default 1e-9). */
 int omm_set_mixed_tol(omm_ctx *ctx, double tol);
 
-/* Line searches between FP64 resynchronizations of OMM_BF16X3 + refinement (default 40). */
+/* Line searches between FP64 resynchronizations of OMM_BF16X3 + refinement (default 80). */
 int omm_set_resync(omm_ctx *ctx, int every);
 
 /* Use `hip_stream` (a hipStream_t) for all work; NULL restores the context's own stream. */
@@ -145,8 +145,10 @@ int omm_checkpoints(omm_ctx *ctx, int *iters, double *energies, int cap, int *n)
 int omm_energy_trace(omm_ctx *ctx, double *buf, int cap, int *n);
 
 /* Diagnostics: with profiling on, every line search records HIP events on the context's stream
- * around its 7 stages (gradient GEMM, P GEMM, Polak-Ribiere + direction, [HD|SD] GEMM,
- * projection GEMM, coefficients + line minimum, updates + energy). Turning it on (or off) resets
+ * around its 7 stages (gradient GEMM, P GEMM, Polak-Ribiere + direction, [HD|SD] GEMM alone,
+ * projection GEMM with the bf16 splits of HD and SD, coefficients + line minimum, updates +
+ * energy). Line searches replayed from a captured graph are not profiled: profiling turns graph
+ * replay off. Turning it on (or off) resets
  * the sums. omm_stage_times writes min(cap, 7) accumulated stage times in ms and the number of
  * profiled line searches, and returns the number of stages (7). */
 int omm_set_profiling(omm_ctx *ctx, int on);

@@ -93,7 +93,7 @@ struct omm_ctx {
   bool phase_active = false;
   int phase_prec = OMM_FP64;  // precision of the active phase
   bool phase_mixed64 = false; // active phase: BF16x3 products on an FP64 state (with resyncs)
-  int resync_every = 40;      // line searches between FP64 resynchronizations
+  int resync_every = 80;      // line searches between FP64 resynchronizations
   int since_resync = 0;
   double resync_E = 0.0;      // FP64 energy at the last resynchronization
   std::vector<int> ck_iter;   // FP64-exact energies of the mixed scheme: (line search, E)
@@ -671,12 +671,12 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     GemmOp ops[2] = {make_op2(M, N, N, Dop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HD, N),
                      make_op2(M, N, N, Dop, N, bf ? pl(c->S_p) : dn(S), N, w.SD, N)};
     TRY(gemm(c, d, ops, 2, done));
-    if (bf) {
-      TRY(split(c, w.HD, c->HD_p, mn));
-      TRY(split(c, w.SD, c->SD_p, mn));
-    }
   }
   TRY(prof_mark(c));
+  if (bf) {  // the projection stage's operand planes
+    TRY(split(c, w.HD, c->HD_p, mn));
+    TRY(split(c, w.SD, c->SD_p, mn));
+  }
   {
     GemmDesc d{cD, ot, ot, T_F64, T_F64, KC, KC, 0, 1};
     GemmOp ops[4] = {make_op2(M, M, N, Dop, N, bf ? pl(c->HC_p) : dn(w.HC), N, c->H1, M),

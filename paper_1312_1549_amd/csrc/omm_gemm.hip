@@ -134,8 +134,8 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
       if (e != hipSuccess || a.W == 0) return e;
       sk_fixup_fn fx = dd.tc == T_F64 ? gemm_sk_fixup<double, double> : gemm_sk_fixup<float, float>;
       if ((dd.tc == T_F64) != (dd.tx == T_F64)) return hipErrorInvalidValue;
-      hipLaunchKernelGGL(fx, dim3(a.T - a.R * SK_GRID), dim3(512), 0, s, b, done, a, SK_GRID,
-                         (const float*)parts);
+      hipLaunchKernelGGL(fx, dim3(a.T - a.R * SK_GRID, SK_FIX_CHUNKS), dim3(256), 0, s, b, done, a,
+                         SK_GRID, (const float*)parts);
       return hipGetLastError();
     }
     dd.tile = 4;  // same 256 x 256 tile on the register path, one workgroup per tile

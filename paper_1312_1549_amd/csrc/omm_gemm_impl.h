@@ -709,6 +709,8 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_dma(GemmBatch batch, const
 // [h W / G, (h + 1) W / G), at most two tile parts since W / G < nk. A part that is not a whole
 // tile leaves its FP32 accumulators in workspace slot 2 h (the first part of h's range) or
 // 2 h + 1 (the second); gemm_sk_fixup sums the parts of each cut tile in K order.
+constexpr int SK_GRID = 256;  // one workgroup per CU
+
 struct SkArgs {
   int T;       // tile-ops
   int nk;      // K steps per tile
@@ -776,38 +778,53 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_sk(GemmBatch batch, const 
   }
 }
 
-// Sums the parts of cut tile blockIdx.x in K order (FP64) and applies the epilogue. Parts and
-// the element each thread owns follow the layout gemm_kernel_sk writes.
+// Sums the parts of cut tile blockIdx.x in K order (FP64) and applies the epilogue; blockIdx.y
+// takes one of SK_FIX_CHUNKS slices of the tile's elements. Parts and the element each slot
+// entry belongs to follow the layout gemm_kernel_sk writes (entry (i TN + j) 4 + r of thread t
+// at offset ((i TN + j) 4 + r) 512 + t).
+constexpr int SK_FIX_CHUNKS = 8;
+
 template <typename TC, typename TX>
-__global__ __launch_bounds__(512) void gemm_sk_fixup(GemmBatch batch, const int* done, SkArgs a,
+__global__ __launch_bounds__(256) void gemm_sk_fixup(GemmBatch batch, const int* done, SkArgs a,
                                                      int G, const float* parts) {
   if (done && *done) return;
+  __shared__ int slot[SK_GRID];
+  __shared__ int nslot;
   const int q = blockIdx.x;
+  const int64_t s0 = (int64_t)q * a.nk, s1 = s0 + a.nk;
+  if (threadIdx.x == 0) {
+    // workgroups (in schedule order h) whose share meets [s0, s1), in K order
+    int h = (int)((s0 * G) / a.W);
+    while (h > 0 && sk_bound(a.W, h, G) > s0) --h;
+    while (sk_bound(a.W, h + 1, G) <= s0) ++h;
+    int n = 0;
+    if (sk_bound(a.W, h + 1, G) < s1) {  // else one workgroup had the whole tile and stored it
+      for (; h < G && sk_bound(a.W, h, G) < s1; ++h) {
+        const int64_t b = sk_bound(a.W, h, G);
+        if (sk_bound(a.W, h + 1, G) <= b) continue;  // empty share
+        slot[n++] = 2 * h + (b < s0 ? 1 : 0);
+      }
+    }
+    nslot = n;
+  }
+  __syncthreads();
+  const int n = nslot;
+  if (n == 0) return;
   const GemmOp& op0 = batch.op[0];
   const int tiles_m = (op0.M + DMA_BM - 1) / DMA_BM, tiles_n = (op0.N + DMA_BN - 1) / DMA_BN;
   const int per_op = tiles_m * tiles_n;
   const int to = a.R * G + q, z = to / per_op, t = to % per_op;
   const GemmOp& op = batch.op[z];
   const int tm = t % tiles_m, tn = t / tiles_m;
-  const int64_t s0 = (int64_t)q * a.nk, s1 = s0 + a.nk;
-  // workgroups (in schedule order h) whose share meets [s0, s1)
-  int hA = (int)((s0 * G) / a.W);
-  while (hA > 0 && sk_bound(a.W, hA, G) > s0) --hA;
-  while (sk_bound(a.W, hA + 1, G) <= s0) ++hA;
-  if (sk_bound(a.W, hA + 1, G) >= s1) return;  // one workgroup had the whole tile and stored it
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = tm * DMA_BM + (wave % 2) * DMA_TM * 16, c0 = tn * DMA_BN + (wave / 2) * DMA_TN * 16;
-  for (int e = 0; e < DMA_TM * DMA_TN * 4; ++e) {
+  constexpr int PER = DMA_BM * DMA_BN / SK_FIX_CHUNKS;
+  for (int f = blockIdx.y * PER + threadIdx.x; f < (blockIdx.y + 1) * PER; f += 256) {
     double sum = 0.0;
-    for (int hh = hA; hh < G && sk_bound(a.W, hh, G) < s1; ++hh) {
-      const int64_t b = sk_bound(a.W, hh, G);
-      if (sk_bound(a.W, hh + 1, G) <= b) continue;  // empty share
-      const int slot = 2 * hh + (b < s0 ? 1 : 0);
-      sum += (double)parts[(int64_t)slot * (DMA_BM * DMA_BN) + e * 512 + threadIdx.x];
-    }
+    for (int k = 0; k < n; ++k) sum += (double)parts[(int64_t)slot[k] * (DMA_BM * DMA_BN) + f];
+    const int e = f >> 9, tid = f & 511;  // slot entry and the kernel thread that wrote it
+    const int wave = tid >> 6, lane = tid & 63;
     const int i = e / (DMA_TN * 4), j = (e / 4) % DMA_TN, r = e % 4;
-    const int row = r0 + i * 16 + 4 * (lane >> 4) + r;
-    const int col = c0 + j * 16 + (lane & 15);
+    const int row = tm * DMA_BM + (wave % 2) * DMA_TM * 16 + i * 16 + 4 * (lane >> 4) + r;
+    const int col = tn * DMA_BN + (wave / 2) * DMA_TN * 16 + j * 16 + (lane & 15);
     if (row < op.M && col < op.N) {
       double v = op.alpha * sum;
       if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
@@ -880,7 +897,6 @@ sk_fn pick_sk_kernel() {
 //       cut evenly across the workgroups).
 constexpr int NTILES = 7;
 constexpr int NTILES_GROUPED = 5;
-constexpr int SK_GRID = 256;  // one workgroup per CU
 inline bool tile_big(int t, int mode) { return t >= 4 && is_bf16_mode(mode); }
 inline int tile_bm(int t, int mode) {
   return t == 1 ? 64 : (t == 2 || tile_big(t, mode) ? 256 : 128);
