@@ -72,8 +72,9 @@ def measured_traffic(workload, precision):
     return d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
 
 
-def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=False, resync=20):
-    solver = OMM(s.N, s.M, precision=prec, refine=refine, resync=resync)
+def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=False, resync=20,
+                    flavour="dense"):
+    solver = OMM(s.N, s.M, precision=prec, refine=refine, resync=resync, flavour=flavour)
     solver.set_HS(dev["H"], dev["S"], dev["T"])
     t0 = time.perf_counter()
     solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # setup only
@@ -97,15 +98,15 @@ def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=
     return wall, setup_s, stages
 
 
-def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, resync):
+def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, resync, flavour="dense"):
     """Wall time from omm_minimize entry (P already built) to the first FP64-exact energy within
     `target` of the closed-form minimum E_ref. The run proceeds in chunks of `resync` line
     searches (omm_iterate) and stops at the first chunk that reaches the target."""
     mixed = prec != "fp64"
-    solver = OMM(s.N, s.M, precision=prec, refine=True, resync=resync)
+    solver = OMM(s.N, s.M, precision=prec, refine=True, resync=resync, flavour=flavour)
     solver.set_HS(dev["H"], dev["S"], dev["T"])
     t0 = time.perf_counter()
-    solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # builds P
+    solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # builds P (or L)
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
     log_every = max(1, 200 // resync)
@@ -248,6 +249,8 @@ def main():
     ap.add_argument("--no-converge", action="store_true", help="skip time-to-converged runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison rate")
+    ap.add_argument("--no-cholesky", action="store_true",
+                    help="skip the Cholesky-reduced flavour's rate and time to converged")
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--resync", type=int, default=80)
     ap.add_argument("--cpu-iters", type=int, default=2)
@@ -293,6 +296,18 @@ def main():
         fp64 = {"iters_per_s": max(3, args.steps // 4) / w64, "stages_ms": st64}
         log(f"fp64: {fp64['iters_per_s']:.3f} iters/s")
 
+    chol = None
+    if not args.no_cholesky and mixed:
+        log(f"timing the Cholesky-reduced flavour ({args.precision})")
+        wc, setup_c, stc = time_iterations(OMM, torch, dev, s, args.precision, args.steps,
+                                           args.warmup, prof_steps, refine=True,
+                                           resync=args.resync, flavour="cholesky")
+        chol = {"iters_per_s": args.steps / wc, "setup_s": setup_c, "stages_ms": stc,
+                "note": "Cholesky-reduced flavour: S = L L^T once, no S or P products per line "
+                        "search; its iterates are those of P = S^-1 (tau = inf), not of tau = "
+                        f"{s.tau}"}
+        log(f"cholesky: {chol['iters_per_s']:.3f} iters/s, setup {setup_c:.2f} s")
+
     op_ms = stages["operator_products"]
     op_flops = 2 * 2.0 * s.M * s.N * s.N
     achieved = op_flops / (op_ms * 1e-3) / 1e12
@@ -322,6 +337,8 @@ def main():
     }
     if pure:
         result["fp32_state_no_resync_iters_per_s"] = pure
+    if chol:
+        result["cholesky_flavour"] = chol
     if fp64:
         result["fp64_iters_per_s"] = fp64["iters_per_s"]
         result["fp64_stages_ms"] = fp64["stages_ms"]
@@ -333,7 +350,7 @@ def main():
             log("no stored closed-form energy for these inputs: skipping time-to-converged")
         else:
             conv = {}
-            log("time to converged: fp64 (1e-8 and 1e-10)")
+            log("time to converged: fp64 (1e-8)")
             conv["fp64_1e-8"] = time_to_converged(OMM, torch, dev, s, "fp64", E_ref, 1e-8,
                                                   args.max_iter, args.resync)
             if args.precision != "fp64":
@@ -344,6 +361,11 @@ def main():
                 b = conv[args.precision + "_1e-8"].get("time_to_target_s")
                 if a and b:
                     conv["mixed_speedup_1e-8"] = a / b
+                if chol:
+                    log(f"time to converged: Cholesky-reduced flavour, {args.precision} (1e-8)")
+                    chol["time_to_converged_1e-8"] = time_to_converged(
+                        OMM, torch, dev, s, args.precision, E_ref, 1e-8, 2 * args.max_iter,
+                        args.resync, flavour="cholesky")
             conv["E_ref"] = E_ref
             result["time_to_converged"] = conv
 

@@ -77,6 +77,21 @@ int omm_set_mixed_tol(omm_ctx *ctx, double tol);
 /* Line searches between FP64 resynchronizations of OMM_BF16X3 + refinement (default 80). */
 int omm_set_resync(omm_ctx *ctx, int every);
 
+/* Flavours of the minimization (Sec. 2.4 and the flavours compared in Sec. 3.1). */
+enum {
+  OMM_FLAVOUR_DENSE = 0,    /* the generalized problem with the preconditioner chosen by tau */
+  OMM_FLAVOUR_CHOLESKY = 1  /* Cholesky-reduced: S = L L^T, minimize over C~ = C L with
+                               H~ = L^-1 (H - eta S) L^-T and S~ = I (no S products, no P product);
+                               the iterates are those of the S^-1-preconditioned dense flavour */
+};
+
+/* Select the flavour (OMM_FLAVOUR_DENSE default). With OMM_FLAVOUR_CHOLESKY omm_minimize ignores
+ * tau, factorizes S once per omm_set_HS (OMM_E_PRECON if S is not positive definite), and
+ * transforms C0 in and C out: omm_get_C, omm_density, omm_edm and omm_backward_device work in the
+ * original basis, omm_get_subspace and the energy are basis independent. Changing the flavour
+ * ends the active minimization; the next omm_minimize needs a C0. */
+int omm_set_flavour(omm_ctx *ctx, int flavour);
+
 /* Use `hip_stream` (a hipStream_t) for all work; NULL restores the context's own stream. */
 int omm_set_stream(omm_ctx *ctx, void *hip_stream);
 

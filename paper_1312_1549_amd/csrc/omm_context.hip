@@ -86,9 +86,17 @@ struct omm_ctx {
   int trace_cap = 0;
   double* nn_scratch = nullptr;  // N x N FP64 (density / EDM / preconditioner work)
   double* inv_work = nullptr;
+  // Cholesky-reduced flavour: S = L L^T, the CG runs on C~ = C L with H~ = L^-1 Hs L^-T (held in
+  // Hs and its derived copies) and S~ = I
+  int flavour = OMM_FLAVOUR_DENSE;
+  double *L = nullptr, *Linv = nullptr;
+  bool l_valid = false;
+  bool hs_reduced = false;      // Hs (and its planes / FP32 copy) holds H~
+  double* Corig = nullptr;      // M x N: C = C~ L^-1 for the outputs
 
   bool have_C = false;
   int c_prec = OMM_FP64;  // precision in which the current C lives
+  int c_flavour = OMM_FLAVOUR_DENSE;  // coordinates of the current C (C~ = C L when reduced)
   // active CG phase (continued by omm_iterate)
   bool phase_active = false;
   int phase_prec = OMM_FP64;  // precision of the active phase
@@ -407,6 +415,7 @@ int ensure_inputs(omm_ctx* c) {
 
 void invalidate(omm_ctx* c) {
   drop_graph(c);
+  c->l_valid = false;
   c->phase_active = false;
   c->phase_mixed64 = false;
   c->hsp_valid = false;
@@ -419,14 +428,49 @@ void invalidate(omm_ctx* c) {
   c->p32_valid = false;
 }
 
-// Hs = H - eta S (Sec. 2.2, Eq. 9) and, for mixed modes, FP32 copies of Hs and S.
+bool reduced(const omm_ctx* c) { return c->flavour == OMM_FLAVOUR_CHOLESKY; }
+
+// S = L L^T and L^-1 for the Cholesky-reduced flavour (Sec. 2.4), once per S.
+int prepare_cholesky(omm_ctx* c) {
+  if (c->l_valid) return OMM_OK;
+  const size_t nn = (size_t)c->N * c->N;
+  TRY(dalloc(c, &c->L, nn));
+  TRY(dalloc(c, &c->Linv, nn));
+  TRY(dalloc(c, &c->inv_work, std::max(invert_work_doubles(c->N), cholesky_work_doubles())));
+  HIPCHK(c, copy_f64(c->S, c->L, (int64_t)nn, c->stream));
+  int bad = 0;
+  HIPCHK(c, cholesky_in_place(c->L, c->N, c->inv_work, c->stream, &bad));
+  if (bad) return fail(c, OMM_E_PRECON, "Cholesky factorization of S failed: S is not positive definite");
+  HIPCHK(c, copy_f64(c->L, c->Linv, (int64_t)nn, c->stream));
+  HIPCHK(c, invert_in_place(c->Linv, c->N, c->inv_work, c->stream, &bad));
+  if (bad) return fail(c, OMM_E_PRECON, "inverting the Cholesky factor hit a zero or non-finite pivot");
+  c->l_valid = true;
+  return OMM_OK;
+}
+
+// Hs = H - eta S (Sec. 2.2, Eq. 9) and, for mixed modes, FP32 copies of Hs and S. In the
+// Cholesky-reduced flavour Hs is replaced by H~ = L^-1 (H - eta S) L^-T.
 int prepare_shift(omm_ctx* c, double eta) {
   const size_t nn = (size_t)c->N * c->N;
-  if (!c->hs_valid || c->hs_eta != eta) {
+  const bool red = reduced(c);
+  if (red) TRY(prepare_cholesky(c));
+  if (!c->hs_valid || c->hs_eta != eta || c->hs_reduced != red) {
     TRY(dalloc(c, &c->Hs, nn));
     HIPCHK(c, shift_hamiltonian(c->H, c->S, eta, c->Hs, (int64_t)nn, c->stream));
+    if (red) {
+      const int N = (int)c->N;
+      TRY(dalloc(c, &c->nn_scratch, nn));
+      // X = L^-1 Hs (B(n, k) = Hs[k][n] = Hs[n][k]), then H~ = X L^-T (B(n, k) = L^-1[n][k])
+      GemmDesc d{CF64, T_F64, T_F64, T_F64, T_F64, KC, KC, 0, 1};
+      GemmOp op = make_op(N, N, N, c->Linv, N, c->Hs, N, c->nn_scratch, N);
+      TRY(gemm(c, d, &op, 1, nullptr, true));
+      GemmOp op2 = make_op(N, N, N, c->nn_scratch, N, c->Linv, N, c->Hs, N);
+      TRY(gemm(c, d, &op2, 1, nullptr, true));
+      HIPCHK(c, symmetrize(c->Hs, N, c->stream));
+    }
     c->hs_valid = true;
     c->hs_eta = eta;
+    c->hs_reduced = red;
     c->hs32_valid = false;
     c->hsp_valid = false;
   }
@@ -436,7 +480,7 @@ int prepare_shift(omm_ctx* c, double eta) {
       HIPCHK(c, split_bf16(c->Hs, c->Hs_p.hi, c->Hs_p.lo, (int64_t)nn, nullptr, c->stream));
       c->hsp_valid = true;
     }
-    if (!c->sp_valid) {
+    if (!c->sp_valid && !red) {
       TRY(alloc_plane(c, c->S_p, nn));
       HIPCHK(c, split_bf16(c->S, c->S_p.hi, c->S_p.lo, (int64_t)nn, nullptr, c->stream));
       c->sp_valid = true;
@@ -447,7 +491,7 @@ int prepare_shift(omm_ctx* c, double eta) {
       HIPCHK(c, convert_f64_f32(c->Hs, c->Hs32, (int64_t)nn, c->stream));
       c->hs32_valid = true;
     }
-    if (!c->s32_valid) {
+    if (!c->s32_valid && !red) {
       TRY(dalloc(c, &c->S32, nn));
       HIPCHK(c, convert_f64_f32(c->S, c->S32, (int64_t)nn, c->stream));
       c->s32_valid = true;
@@ -458,7 +502,8 @@ int prepare_shift(omm_ctx* c, double eta) {
 
 // P = (S + T/tau)^-1, S^-1 or I (Sec. 2.4, Eq. 17), factorized once per (S, T, tau).
 int prepare_precon(omm_ctx* c, double tau) {
-  int kind = !(tau > 0.0) ? 0 : (isinf(tau) ? 1 : 2);
+  // the Cholesky-reduced flavour needs none: S~ = I, and CG on C~ is the S^-1-preconditioned CG
+  int kind = reduced(c) || !(tau > 0.0) ? 0 : (isinf(tau) ? 1 : 2);
   if (kind == 2 && !c->have_T)
     return fail(c, OMM_E_ARG, "a finite tau > 0 needs the kinetic matrix T");
   const size_t nn = (size_t)c->N * c->N;
@@ -577,7 +622,12 @@ int initial_products(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* 
   GemmDesc d{compute, et, et, elem_type<T>(), elem_type<T>(), KC, KC, 0, 1};
   GemmOp ops[2] = {make_op2(M, N, N, Cop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HC, N),
                    make_op2(M, N, N, Cop, N, bf ? pl(c->S_p) : dn(S), N, w.SC, N)};
-  TRY(gemm(c, d, ops, 2, nullptr));
+  // reduced problem (S~ = I): SC = C, kept as its own copy, which every update then moves
+  // exactly like C
+  const bool sid = reduced(c);
+  TRY(gemm(c, d, ops, sid ? 1 : 2, nullptr));
+  if (sid)
+    HIPCHK(c, hipMemcpyAsync(w.SC, w.C, mn * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
   if (bf) TRY(split_state(c, w.HC, w.SC, false));
   GemmDesc d2{compute, et, et, T_F64, T_F64, KC, KC, 0, 1};
   GemmOp ops2[2] = {make_op2(M, M, N, bf ? pl(c->HC_p) : dn(w.HC), N, Cop, N, c->HW, M),
@@ -666,30 +716,34 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
                                   c->stream, bf ? c->D_p.hi : nullptr));
   TRY(prof_mark(c));
   const Opnd Dop = bf ? pl(c->D_p) : dn(w.D);
+  // reduced problem (S~ = I): SD = D, no product
+  const bool sid = reduced(c);
+  T* SD = sid ? w.D : w.SD;
   {
     GemmDesc d{cD, ot, ot, et, et, KC, KC, 0, 1};
     GemmOp ops[2] = {make_op2(M, N, N, Dop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HD, N),
                      make_op2(M, N, N, Dop, N, bf ? pl(c->S_p) : dn(S), N, w.SD, N)};
-    TRY(gemm(c, d, ops, 2, done));
+    TRY(gemm(c, d, ops, sid ? 1 : 2, done));
   }
   TRY(prof_mark(c));
-  if (bf) {  // the projection stage's operand planes
+  if (bf) {  // the projection stage's operand planes (D's lo plane stays zero)
     TRY(split(c, w.HD, c->HD_p, mn));
-    TRY(split(c, w.SD, c->SD_p, mn));
+    if (!sid) TRY(split(c, w.SD, c->SD_p, mn));
   }
+  const Plane& SD_p = sid ? c->D_p : c->SD_p;
   {
     GemmDesc d{cD, ot, ot, T_F64, T_F64, KC, KC, 0, 1};
     GemmOp ops[4] = {make_op2(M, M, N, Dop, N, bf ? pl(c->HC_p) : dn(w.HC), N, c->H1, M),
                      make_op2(M, M, N, Dop, N, bf ? pl(c->SC_p) : dn(w.SC), N, c->S1, M),
                      make_op2(M, M, N, Dop, N, bf ? pl(c->HD_p) : dn(w.HD), N, c->H2, M),
-                     make_op2(M, M, N, Dop, N, bf ? pl(c->SD_p) : dn(w.SD), N, c->S2, M)};
+                     make_op2(M, M, N, Dop, N, bf ? pl(SD_p) : dn(SD), N, c->S2, M)};
     TRY(gemm(c, d, ops, 4, done));
   }
   TRY(prof_mark(c));
   HIPCHK(c, line_search(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
                         c->stream));
   TRY(prof_mark(c));
-  HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, w.SD, mn, c->st, c->stream));
+  HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, mn, c->st, c->stream));
   if (bf) TRY(split_state(c, w.HC, w.SC));
   HIPCHK(c, update_subspace(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
                             trace, c->stream));
@@ -828,9 +882,13 @@ int resync_fp64(omm_ctx* c) {
   const int M = (int)c->M, N = (int)c->N;
   Work<double>& w = c->w64;
   GemmDesc d{CF64, T_F64, T_F64, T_F64, T_F64, KC, KC, 0, 1};
+  const bool sid = reduced(c);
   GemmOp ops[2] = {make_op(M, N, N, w.C, N, c->Hs, N, w.HC, N),
                    make_op(M, N, N, w.C, N, c->S, N, w.SC, N)};
-  TRY(gemm(c, d, ops, 2, nullptr));
+  TRY(gemm(c, d, ops, sid ? 1 : 2, nullptr));
+  if (sid)
+    HIPCHK(c, hipMemcpyAsync(w.SC, w.C, (size_t)M * N * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
   GemmOp ops2[2] = {make_op(M, M, N, w.HC, N, w.C, N, c->HW, M),
                     make_op(M, M, N, w.SC, N, w.C, N, c->SW, M)};
   TRY(gemm(c, d, ops2, 2, nullptr));
@@ -905,6 +963,8 @@ int minimize_impl(omm_ctx* c, const double* C0, bool C0_device, double eta, doub
   if (!(tol >= 0.0) || max_iter < 0 || !std::isfinite(eta) || std::isnan(tau))
     return fail(c, OMM_E_ARG, "need tol >= 0, max_iter >= 0, finite eta, non-NaN tau");
   if (!C0 && !c->have_C) return fail(c, OMM_E_STATE, "no C0 given and no C to resume from");
+  if (!C0 && c->c_flavour != c->flavour)
+    return fail(c, OMM_E_STATE, "the flavour changed since the last minimization: pass C0");
   const size_t mn = (size_t)c->M * c->N;
   TRY(alloc_common(c));
   TRY(alloc_work<double>(c, c->w64));
@@ -919,6 +979,15 @@ int minimize_impl(omm_ctx* c, const double* C0, bool C0_device, double eta, doub
     if (C0_device) HIPCHK(c, hipMemcpyAsync(c->w64.C, C0, mn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     else HIPCHK(c, hipMemcpyAsync(c->w64.C, C0, mn * sizeof(double), hipMemcpyHostToDevice, c->stream));
     c->c_prec = OMM_FP64;
+    if (reduced(c)) {  // C~0 = C0 L: B(n, k) = L[k][n] (RC)
+      const int M = (int)c->M, N = (int)c->N;
+      GemmDesc d{CF64, T_F64, T_F64, T_F64, T_F64, KC, RC, 0, 1};
+      GemmOp op = make_op(M, N, N, c->w64.C, N, c->L, N, c->w64.HD, N);
+      TRY(gemm(c, d, &op, 1, nullptr));
+      HIPCHK(c, hipMemcpyAsync(c->w64.C, c->w64.HD, mn * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    }
+    c->c_flavour = c->flavour;
   }
   if (c->mode != OMM_FP64 && !mixed64 && c->c_prec == OMM_FP64)
     HIPCHK(c, convert_f64_f32(c->w64.C, c->w32.C, (int64_t)mn, c->stream));
@@ -997,21 +1066,39 @@ int c64(omm_ctx* c) {
   return OMM_OK;
 }
 
+// C in the original basis (FP64): the working C, or C = C~ L^-1 in the reduced flavour.
+int c_original(omm_ctx* c, const double** out) {
+  TRY(c64(c));
+  if (c->c_flavour != OMM_FLAVOUR_CHOLESKY) {
+    *out = c->w64.C;
+    return OMM_OK;
+  }
+  if (!c->l_valid) return fail(c, OMM_E_STATE, "the Cholesky factor is gone (new S): minimize again");
+  const int M = (int)c->M, N = (int)c->N;
+  TRY(dalloc(c, &c->Corig, (size_t)M * N));
+  GemmDesc d{CF64, T_F64, T_F64, T_F64, T_F64, KC, RC, 0, 1};  // B(n, k) = L^-1[k][n]
+  GemmOp op = make_op(M, N, N, c->w64.C, N, c->Linv, N, c->Corig, N);
+  TRY(gemm(c, d, &op, 1, nullptr));
+  *out = c->Corig;
+  return OMM_OK;
+}
+
 // out = scale * C^T X C-style products: rho = 2 C^T (2I - SW) C, EDM = 2 C^T HW C.
 int ct_x_c(omm_ctx* c, const double* Xmm, double diag_for_identity, bool use_identity,
            double* out) {
-  TRY(c64(c));
+  const double* Cb = nullptr;
+  TRY(c_original(c, &Cb));
   const int M = (int)c->M, N = (int)c->N;
   double* Y = c->H1;  // M x M scratch
   if (use_identity) HIPCHK(c, identity_minus(Xmm, Y, M, diag_for_identity, 1.0, c->stream));
   else HIPCHK(c, copy_f64(Xmm, Y, (int64_t)M * M, c->stream));
   double* Z = c->w64.HD;  // M x N scratch: Z = Y C
   GemmDesc d{CF64, T_F64, T_F64, T_F64, T_F64, KC, RC, 0, 1};
-  GemmOp op = make_op(M, N, M, Y, M, c->w64.C, N, Z, N);
+  GemmOp op = make_op(M, N, M, Y, M, Cb, N, Z, N);
   TRY(gemm(c, d, &op, 1, nullptr));
   // out = 2 C^T Z : A(m, k) = C[k, m] (RC), B(k, n) = Z[k, n] (RC)
   GemmDesc d2{CF64, T_F64, T_F64, T_F64, T_F64, RC, RC, 0, 1};
-  GemmOp op2 = make_op(N, N, M, c->w64.C, N, Z, N, out, N, 2.0);
+  GemmOp op2 = make_op(N, N, M, Cb, N, Z, N, out, N, 2.0);
   TRY(gemm(c, d2, &op2, 1, nullptr));
   return OMM_OK;
 }
@@ -1059,6 +1146,7 @@ int omm_destroy(omm_ctx* c) {
   dfree(c->HW); dfree(c->SW); dfree(c->H1); dfree(c->S1); dfree(c->H2); dfree(c->S2);
   dfree(c->partials); dfree(c->ws); dfree(c->st); dfree(c->flags); dfree(c->trace);
   dfree(c->nn_scratch); dfree(c->inv_work);
+  dfree(c->L); dfree(c->Linv); dfree(c->Corig);
   if (c->st_host) hipHostFree(c->st_host);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own) hipStreamDestroy(c->own);
@@ -1072,6 +1160,19 @@ int omm_set_precision(omm_ctx* c, int mode, int fp64_refine) {
     return fail(c, OMM_E_ARG, "unknown precision mode");
   c->mode = mode;
   c->refine = fp64_refine ? 1 : 0;
+  return OMM_OK;
+}
+
+int omm_set_flavour(omm_ctx* c, int flavour) {
+  if (!c) return OMM_E_ARG;
+  if (flavour != OMM_FLAVOUR_DENSE && flavour != OMM_FLAVOUR_CHOLESKY)
+    return fail(c, OMM_E_ARG, "unknown flavour");
+  if (flavour != c->flavour) {
+    drop_graph(c);
+    c->flavour = flavour;
+    c->phase_active = false;
+    c->phase_mixed64 = false;
+  }
   return OMM_OK;
 }
 
@@ -1252,8 +1353,9 @@ int omm_backward_device(omm_ctx* c, double gE, double* d_gH, double* d_gS) {
 
 int omm_get_C(omm_ctx* c, double* C) {
   if (!c || !C) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
-  TRY(c64(c));
-  HIPCHK(c, hipMemcpyAsync(C, c->w64.C, (size_t)c->M * c->N * sizeof(double),
+  const double* Cb = nullptr;
+  TRY(c_original(c, &Cb));
+  HIPCHK(c, hipMemcpyAsync(C, Cb, (size_t)c->M * c->N * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return OMM_OK;

@@ -153,5 +153,9 @@ hipError_t group_update(const SysDev* d_sys, int nsys, hipStream_t s);
 // sets *bad (host) to 1 if a pivot block was singular or a non-finite value appeared.
 hipError_t invert_in_place(double* A, int64_t n, double* work, hipStream_t s, int* bad);
 size_t invert_work_doubles(int64_t n);
+// Cholesky factorization S = L L^T in place (L lower, strict upper set to zero); *bad != 0 when
+// a pivot is not positive (S not positive definite) or the result is not finite.
+hipError_t cholesky_in_place(double* A, int64_t n, double* work, hipStream_t s, int* bad);
+size_t cholesky_work_doubles();
 
 }  // namespace omm

@@ -23,6 +23,7 @@ ERRORS = {
     -9: "OMM_E_ASYMMETRIC",
 }
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+FLAVOURS = {"dense": 0, "cholesky": 1}
 
 
 class OMMError(RuntimeError):
@@ -54,7 +55,7 @@ class OMM:
 
     def __init__(self, N: int, M: int, precision: str = "fp64", refine: bool = True,
                  mixed_tol: Optional[float] = None, use_torch_stream: bool = True,
-                 resync: Optional[int] = None):
+                 resync: Optional[int] = None, flavour: str = "dense"):
         self._L = lib()
         self.N, self.M = int(N), int(M)
         h = ct.c_void_p()
@@ -67,6 +68,7 @@ class OMM:
             self._check(self._L.omm_set_mixed_tol(self._h, float(mixed_tol)))
         if resync is not None:
             self._check(self._L.omm_set_resync(self._h, int(resync)))
+        self.set_flavour(flavour)
         self._use_torch_stream = use_torch_stream
 
     # -- plumbing --------------------------------------------------------------------------
@@ -104,6 +106,13 @@ class OMM:
     # -- API ---------------------------------------------------------------------------------
     def set_precision(self, precision: str = "fp64", refine: bool = True):
         self._check(self._L.omm_set_precision(self._h, PRECISIONS[precision], 1 if refine else 0))
+
+    def set_flavour(self, flavour: str):
+        """"dense" (the generalized problem, preconditioner from tau) or "cholesky" (the
+        Cholesky-reduced problem; tau is ignored, outputs are in the original basis)."""
+        if flavour not in FLAVOURS:
+            raise ValueError(f"flavour must be one of {sorted(FLAVOURS)}")
+        self._check(self._L.omm_set_flavour(self._h, FLAVOURS[flavour]))
 
     def set_HS(self, H, S, T=None):
         n = (self.N, self.N)
