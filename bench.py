@@ -73,8 +73,9 @@ def measured_traffic(workload, precision):
 
 
 def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=False, resync=20,
-                    flavour="dense"):
-    solver = OMM(s.N, s.M, precision=prec, refine=refine, resync=resync, flavour=flavour)
+                    flavour="dense", sparse=False):
+    solver = OMM(s.N, s.M, precision=prec, refine=refine, resync=resync, flavour=flavour,
+                 sparse=sparse)
     solver.set_HS(dev["H"], dev["S"], dev["T"])
     t0 = time.perf_counter()
     solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # setup only
@@ -98,12 +99,14 @@ def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=
     return wall, setup_s, stages
 
 
-def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, resync, flavour="dense"):
+def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, resync, flavour="dense",
+                      sparse=False):
     """Wall time from omm_minimize entry (P already built) to the first FP64-exact energy within
     `target` of the closed-form minimum E_ref. The run proceeds in chunks of `resync` line
     searches (omm_iterate) and stops at the first chunk that reaches the target."""
     mixed = prec != "fp64"
-    solver = OMM(s.N, s.M, precision=prec, refine=True, resync=resync, flavour=flavour)
+    solver = OMM(s.N, s.M, precision=prec, refine=True, resync=resync, flavour=flavour,
+                 sparse=sparse)
     solver.set_HS(dev["H"], dev["S"], dev["T"])
     t0 = time.perf_counter()
     solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # builds P (or L)
@@ -251,6 +254,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison rate")
     ap.add_argument("--no-cholesky", action="store_true",
                     help="skip the Cholesky-reduced flavour's rate and time to converged")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the block-sparse operator products' rate and time to converged")
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--resync", type=int, default=80)
     ap.add_argument("--cpu-iters", type=int, default=2)
@@ -308,6 +313,16 @@ def main():
                         f"{s.tau}"}
         log(f"cholesky: {chol['iters_per_s']:.3f} iters/s, setup {setup_c:.2f} s")
 
+    sparse = None
+    if not args.no_sparse and args.precision == "bf16x3":
+        log("timing block-sparse operator products (bf16x3)")
+        wsp, _, stsp = time_iterations(OMM, torch, dev, s, args.precision, args.steps, args.warmup,
+                                       prof_steps, refine=True, resync=args.resync, sparse=True)
+        sparse = {"iters_per_s": args.steps / wsp, "stages_ms": stsp,
+                  "note": "[HD|SD] over the non-zero 32-deep K blocks of each 256-column tile of Hs "
+                          "and S only; same iterates as the dense products (bitwise, same tile)"}
+        log(f"sparse products: {sparse['iters_per_s']:.3f} iters/s")
+
     op_ms = stages["operator_products"]
     op_flops = 2 * 2.0 * s.M * s.N * s.N
     achieved = op_flops / (op_ms * 1e-3) / 1e12
@@ -339,6 +354,8 @@ def main():
         result["fp32_state_no_resync_iters_per_s"] = pure
     if chol:
         result["cholesky_flavour"] = chol
+    if sparse:
+        result["sparse_operator_products"] = sparse
     if fp64:
         result["fp64_iters_per_s"] = fp64["iters_per_s"]
         result["fp64_stages_ms"] = fp64["stages_ms"]
@@ -361,6 +378,11 @@ def main():
                 b = conv[args.precision + "_1e-8"].get("time_to_target_s")
                 if a and b:
                     conv["mixed_speedup_1e-8"] = a / b
+                if sparse:
+                    log(f"time to converged: block-sparse operator products, {args.precision} (1e-8)")
+                    sparse["time_to_converged_1e-8"] = time_to_converged(
+                        OMM, torch, dev, s, args.precision, E_ref, 1e-8, args.max_iter,
+                        args.resync, sparse=True)
                 if chol:
                     log(f"time to converged: Cholesky-reduced flavour, {args.precision} (1e-8)")
                     chol["time_to_converged_1e-8"] = time_to_converged(

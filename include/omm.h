@@ -92,6 +92,18 @@ enum {
  * ends the active minimization; the next omm_minimize needs a C0. */
 int omm_set_flavour(omm_ctx *ctx, int flavour);
 
+/* Block-sparse operator products (the sparse x dense products of Secs. 2.6 and 3, applied to
+ * [HD | SD] = D [Hs | S] of OMM_BF16X3 in the dense flavour; default off). The finite-range
+ * basis leaves most of Hs and S zero: for every 256-column tile of the product the library lists
+ * the 32-deep K blocks in which the operator is not all zero (built once per Hs and S) and
+ * multiplies over those only. The skipped blocks contribute exact zeros, so the results are the
+ * dense products (up to the sign of zero) and the iterates do not change. Other modes and the
+ * Cholesky flavour (whose H~ is dense) ignore it. */
+int omm_set_sparse(omm_ctx *ctx, int on);
+/* Fraction of K blocks listed for Hs (density[0]) and S (density[1]) after a minimization with
+ * sparse products on; OMM_E_STATE otherwise. */
+int omm_sparse_density(omm_ctx *ctx, double *density);
+
 /* Use `hip_stream` (a hipStream_t) for all work; NULL restores the context's own stream. */
 int omm_set_stream(omm_ctx *ctx, void *hip_stream);
 

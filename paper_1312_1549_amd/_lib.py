@@ -20,6 +20,8 @@ PROTOTYPES = {
     "omm_set_mixed_tol": (ct.c_int, [_vp, ct.c_double]),
     "omm_set_resync": (ct.c_int, [_vp, ct.c_int]),
     "omm_set_flavour": (ct.c_int, [_vp, ct.c_int]),
+    "omm_set_sparse": (ct.c_int, [_vp, ct.c_int]),
+    "omm_sparse_density": (ct.c_int, [_vp, _c_double_p]),
     "omm_checkpoints": (ct.c_int, [_vp, _c_int_p, _c_double_p, ct.c_int, _c_int_p]),
     "omm_set_stream": (ct.c_int, [_vp, _vp]),
     "omm_set_HS": (ct.c_int, [_vp, _vp, _vp, _vp]),

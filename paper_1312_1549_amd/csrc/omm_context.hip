@@ -93,6 +93,12 @@ struct omm_ctx {
   bool l_valid = false;
   bool hs_reduced = false;      // Hs (and its planes / FP32 copy) holds H~
   double* Corig = nullptr;      // M x N: C = C~ L^-1 for the outputs
+  // block-sparse operator products (BF16 scheme, dense flavour): K-block lists of Hs and S
+  bool sparse = false;
+  int* kl_ptr[2] = {nullptr, nullptr};  // Hs, S: per 256-column tile, offsets into kl_idx
+  int* kl_idx[2] = {nullptr, nullptr};
+  bool kl_valid[2] = {false, false};
+  double kl_density[2] = {1.0, 1.0};    // listed K blocks / all K blocks
 
   bool have_C = false;
   int c_prec = OMM_FP64;  // precision in which the current C lives
@@ -343,7 +349,10 @@ int gemm(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, const int* done, bool tu
   GemmDesc df = d;
   df.tile = ft;
   df.splitk = 1;
-  if (ft >= 0 && gemm_supported(df)) {
+  if (ops[0].kptr) {  // block-sparse B: the launcher runs the direct-to-LDS tile, no split
+    d.tile = 5;
+    d.splitk = 1;
+  } else if (ft >= 0 && gemm_supported(df)) {
     d = df;
   } else if (tunable && flops >= 2e9 && autotune_enabled()) {
     TuneKey key{{d.compute, d.ta, d.tb, d.tc, d.tx, d.la, d.lb, M, N, K, nops}};
@@ -416,6 +425,7 @@ int ensure_inputs(omm_ctx* c) {
 void invalidate(omm_ctx* c) {
   drop_graph(c);
   c->l_valid = false;
+  c->kl_valid[0] = c->kl_valid[1] = false;
   c->phase_active = false;
   c->phase_mixed64 = false;
   c->hsp_valid = false;
@@ -429,6 +439,45 @@ void invalidate(omm_ctx* c) {
 }
 
 bool reduced(const omm_ctx* c) { return c->flavour == OMM_FLAVOUR_CHOLESKY; }
+
+// K-block lists of an N x N operator for the block-sparse products (which = 0: Hs, 1: S).
+int build_klist(omm_ctx* c, const double* B, int which) {
+  if (c->kl_valid[which]) return OMM_OK;
+  const int64_t n = c->N;
+  const int nkb = (int)((n + SPARSE_BK - 1) / SPARSE_BK);
+  const int nt = (int)((n + SPARSE_BN - 1) / SPARSE_BN);
+  unsigned char* dflags = nullptr;
+  TRY(dalloc(c, &dflags, (size_t)nkb * nt));
+  HIPCHK(c, block_pattern(B, n, dflags, c->stream));
+  std::vector<unsigned char> flags((size_t)nkb * nt);
+  HIPCHK(c, hipMemcpyAsync(flags.data(), dflags, flags.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  dfree(dflags);
+  std::vector<int> ptr(nt + 1, 0), idx;
+  for (int t = 0; t < nt; ++t) {
+    for (int kb = 0; kb < nkb; ++kb)
+      if (flags[(size_t)t * nkb + kb]) idx.push_back(kb);
+    ptr[t + 1] = (int)idx.size();
+  }
+  if (idx.empty()) idx.push_back(0);  // an all-zero operator still needs a valid array
+  drop_graph(c);
+  dfree(c->kl_ptr[which]);
+  dfree(c->kl_idx[which]);
+  TRY(dalloc(c, &c->kl_ptr[which], ptr.size()));
+  TRY(dalloc(c, &c->kl_idx[which], idx.size()));
+  HIPCHK(c, hipMemcpyAsync(c->kl_ptr[which], ptr.data(), ptr.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->kl_idx[which], idx.data(), idx.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->kl_density[which] = (double)ptr[nt] / ((double)nkb * nt);
+  c->kl_valid[which] = true;
+  return OMM_OK;
+}
+
+bool sparse_products(const omm_ctx* c) {
+  return c->sparse && c->mode == OMM_BF16X3 && !reduced(c);
+}
 
 // S = L L^T and L^-1 for the Cholesky-reduced flavour (Sec. 2.4), once per S.
 int prepare_cholesky(omm_ctx* c) {
@@ -471,6 +520,8 @@ int prepare_shift(omm_ctx* c, double eta) {
     c->hs_valid = true;
     c->hs_eta = eta;
     c->hs_reduced = red;
+    c->kl_valid[0] = false;
+    drop_graph(c);  // a captured graph may hold the old Hs lists
     c->hs32_valid = false;
     c->hsp_valid = false;
   }
@@ -484,6 +535,10 @@ int prepare_shift(omm_ctx* c, double eta) {
       TRY(alloc_plane(c, c->S_p, nn));
       HIPCHK(c, split_bf16(c->S, c->S_p.hi, c->S_p.lo, (int64_t)nn, nullptr, c->stream));
       c->sp_valid = true;
+    }
+    if (sparse_products(c)) {
+      TRY(build_klist(c, c->Hs, 0));
+      TRY(build_klist(c, c->S, 1));
     }
   } else if (c->mode == OMM_FP32) {
     if (!c->hs32_valid) {
@@ -723,6 +778,12 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     GemmDesc d{cD, ot, ot, et, et, KC, KC, 0, 1};
     GemmOp ops[2] = {make_op2(M, N, N, Dop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HD, N),
                      make_op2(M, N, N, Dop, N, bf ? pl(c->S_p) : dn(S), N, w.SD, N)};
+    if (bf && sparse_products(c)) {
+      for (int i = 0; i < 2; ++i) {
+        ops[i].kptr = c->kl_ptr[i];
+        ops[i].kidx = c->kl_idx[i];
+      }
+    }
     TRY(gemm(c, d, ops, sid ? 1 : 2, done));
   }
   TRY(prof_mark(c));
@@ -1147,6 +1208,10 @@ int omm_destroy(omm_ctx* c) {
   dfree(c->partials); dfree(c->ws); dfree(c->st); dfree(c->flags); dfree(c->trace);
   dfree(c->nn_scratch); dfree(c->inv_work);
   dfree(c->L); dfree(c->Linv); dfree(c->Corig);
+  for (int i = 0; i < 2; ++i) {
+    dfree(c->kl_ptr[i]);
+    dfree(c->kl_idx[i]);
+  }
   if (c->st_host) hipHostFree(c->st_host);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own) hipStreamDestroy(c->own);
@@ -1173,6 +1238,24 @@ int omm_set_flavour(omm_ctx* c, int flavour) {
     c->phase_active = false;
     c->phase_mixed64 = false;
   }
+  return OMM_OK;
+}
+
+int omm_set_sparse(omm_ctx* c, int on) {
+  if (!c) return OMM_E_ARG;
+  if ((on != 0) != c->sparse) {
+    drop_graph(c);
+    c->sparse = on != 0;
+  }
+  return OMM_OK;
+}
+
+int omm_sparse_density(omm_ctx* c, double* density) {
+  if (!c || !density) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  if (!c->kl_valid[0] || !c->kl_valid[1])
+    return fail(c, OMM_E_STATE, "no block-sparse lists: enable sparse products and minimize");
+  density[0] = c->kl_density[0];
+  density[1] = c->kl_density[1];
   return OMM_OK;
 }
 

@@ -112,6 +112,16 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
   if (M <= 0 || N <= 0) return hipSuccess;
   if (d.tile < 0 || d.tile >= NTILES) return hipErrorInvalidValue;
   GemmDesc dd = d;
+  bool sparse = false;
+  for (int i = 0; i < nops; ++i) sparse |= ops[i].kptr != nullptr;
+  if (sparse) {
+    // block-sparse B lists are read only by the direct-to-LDS tile over the whole K range
+    for (int i = 0; i < nops; ++i)
+      if (ops[i].nseg != 1 || !ops[i].kidx) return hipErrorInvalidValue;
+    if (!is_bf16_mode(dd.compute) || !dma_ok(dd, ops, nops)) return hipErrorInvalidValue;
+    dd.tile = 5;
+    dd.splitk = 1;
+  }
   if (dd.tile == 6) {
     if (dma_ok(dd, ops, nops)) {
       sk_fn fn = pick_sk(dd);

@@ -543,6 +543,7 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
 // (zero fill). Requires 16-byte aligned plane pointers, leading dimensions that are multiples
 // of 8, and a first segment length that is a multiple of 8 (checked by the launcher).
 constexpr int DMA_BM = 256, DMA_BN = 256, DMA_BK = 32, DMA_PLANE = DMA_BM * DMA_BK;
+static_assert(DMA_BN == SPARSE_BN && DMA_BK == SPARSE_BK, "block-sparse lists follow this tile");
 
 // s_waitcnt: vmcnt <= n, lgkmcnt = 0 (expcnt unconstrained)
 template <int N>
@@ -616,11 +617,15 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
       src[i] = plane[pl] + (int64_t)gr * ldp[pl] + 8 * lchunk;
       dst[i] = pl * DMA_PLANE + 512 * j;
     }
-    const int nst = (ke - kb + BK - 1) / BK;
-    auto full = [&](int st) { return kb + (st + 1) * BK <= ke; };
+    // dense: stages kb, kb + BK, ...; block-sparse B: the listed K blocks of this column tile
+    const bool sparse = op.kptr != nullptr && op.nseg == 1;
+    const int* klist = sparse ? op.kidx + op.kptr[tn] : nullptr;
+    const int nst = sparse ? op.kptr[tn + 1] - op.kptr[tn] : (ke - kb + BK - 1) / BK;
+    auto kstart = [&](int st) { return sparse ? klist[st] * BK : kb + st * BK; };
+    auto full = [&](int st) { return kstart(st) + BK <= ke; };
     auto issue = [&](int st) {
       lds_t* buf = L + (st % NS) * NPL * DMA_PLANE;
-      const int k0 = kb + st * BK;
+      const int k0 = kstart(st);
       if (full(st)) {
 #pragma unroll
         for (int i = 0; i < DPS; ++i)

@@ -51,6 +51,12 @@ struct GemmOp {
   const void* X;       // epilogue addend (may alias C), nullable
   int64_t ldx;
   double alpha, beta;  // C = alpha * sum_seg A_seg B_seg + beta * X
+  // Block-sparse B (one segment, direct-to-LDS tile only; nullable = dense): for column tile t
+  // of the 256-wide output tiling, kidx[kptr[t] .. kptr[t + 1]) are the ascending 32-deep K
+  // blocks in which that tile's rows of B are not all zero. The skipped blocks contribute exact
+  // zeros, so the result equals the dense product (up to the sign of zero).
+  const int* kptr;
+  const int* kidx;
 };
 
 struct GemmDesc {
@@ -68,6 +74,12 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
 size_t gemm_splitk_ws_bytes(const GemmOp* ops, int nops, int splitk);
 // Workspace a launch with descriptor d needs (split-K partials, or stream-K tile parts).
 size_t gemm_ws_bytes(const GemmDesc& d, const GemmOp* ops, int nops);
+// Block pattern of the block-sparse B lists: 256-wide column tiles of the direct-to-LDS GEMM,
+// 32-deep K blocks.
+constexpr int SPARSE_BN = 256, SPARSE_BK = 32;
+// flags[t * nkb + kb] = 1 iff some B[r][k] != 0 with r in column tile t and k in K block kb
+// (B is n x n row-major; nkb = ceil(n / SPARSE_BK)).
+hipError_t block_pattern(const double* B, int64_t n, unsigned char* flags, hipStream_t s);
 int gemm_num_tiles();
 int gemm_grouped_num_tiles();
 bool gemm_supported(const GemmDesc& d);

@@ -265,6 +265,21 @@ __device__ __forceinline__ void b_direction(const T* PG, T* D, int64_t n, int fi
   }
 }
 
+// One block per (K block, column tile): does the SPARSE_BN x SPARSE_BK sub-matrix hold a
+// non-zero?
+__global__ void k_block_pattern(const double* B, int64_t n, unsigned char* flags) {
+  const int kb = blockIdx.x, t = blockIdx.y;
+  const int nkb = gridDim.x;
+  int nz = 0;
+  for (int e = threadIdx.x; e < SPARSE_BN * SPARSE_BK; e += NT) {
+    const int64_t r = (int64_t)t * SPARSE_BN + e / SPARSE_BK;
+    const int64_t k = (int64_t)kb * SPARSE_BK + e % SPARSE_BK;
+    if (r < n && k < n && B[r * n + k] != 0.0) nz = 1;
+  }
+  nz = __syncthreads_or(nz);
+  if (threadIdx.x == 0) flags[(int64_t)t * nkb + kb] = (unsigned char)nz;
+}
+
 template <typename T>
 __global__ void k_direction(const T* PG, T* D, int64_t n, int first, const DevState* st) {
   b_direction(PG, D, n, first, st, blockIdx.x, gridDim.x);
@@ -681,6 +696,13 @@ hipError_t energy_init(const double* HW, const double* SW, int M, double* partia
   const int nb = red_blocks((int64_t)M * M);
   hipLaunchKernelGGL(k_energy_partials, dim3(nb), dim3(NT), 0, s, HW, SW, M, partials);
   hipLaunchKernelGGL(k_energy_init_final, dim3(1), dim3(NT), 0, s, partials, nb, st, trace);
+  return hipGetLastError();
+}
+
+hipError_t block_pattern(const double* B, int64_t n, unsigned char* flags, hipStream_t s) {
+  const int nkb = (int)((n + SPARSE_BK - 1) / SPARSE_BK);
+  const int nt = (int)((n + SPARSE_BN - 1) / SPARSE_BN);
+  hipLaunchKernelGGL(k_block_pattern, dim3(nkb, nt), dim3(NT), 0, s, B, n, flags);
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ class OMM:
 
     def __init__(self, N: int, M: int, precision: str = "fp64", refine: bool = True,
                  mixed_tol: Optional[float] = None, use_torch_stream: bool = True,
-                 resync: Optional[int] = None, flavour: str = "dense"):
+                 resync: Optional[int] = None, flavour: str = "dense", sparse: bool = False):
         self._L = lib()
         self.N, self.M = int(N), int(M)
         h = ct.c_void_p()
@@ -69,6 +69,7 @@ class OMM:
         if resync is not None:
             self._check(self._L.omm_set_resync(self._h, int(resync)))
         self.set_flavour(flavour)
+        self._check(self._L.omm_set_sparse(self._h, 1 if sparse else 0))
         self._use_torch_stream = use_torch_stream
 
     # -- plumbing --------------------------------------------------------------------------
@@ -113,6 +114,12 @@ class OMM:
         if flavour not in FLAVOURS:
             raise ValueError(f"flavour must be one of {sorted(FLAVOURS)}")
         self._check(self._L.omm_set_flavour(self._h, FLAVOURS[flavour]))
+
+    def sparse_density(self):
+        """Fractions of K blocks the block-sparse products visit for (Hs, S)."""
+        d = (ct.c_double * 2)()
+        self._check(self._L.omm_sparse_density(self._h, d))
+        return float(d[0]), float(d[1])
 
     def set_HS(self, H, S, T=None):
         n = (self.N, self.N)
