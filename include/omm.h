@@ -168,6 +168,29 @@ int omm_phase_stats(omm_ctx *ctx, int *mixed_iters, int *fp64_iters);
 /* FP64-exact energies of the OMM_BF16X3 + refinement scheme: the line-search index and energy
  * at the start and at every resynchronization (up to cap; *n = total). */
 int omm_checkpoints(omm_ctx *ctx, int *iters, double *energies, int cap, int *n);
+/* Complex Hermitian problems (a general k-point: the Hermitian forms of Secs. 2.1-2.4). The
+ * context holds the exact real embedding: N x N Hermitian X = A + iB (A symmetric, B
+ * antisymmetric) acts on row vectors [Re c, Im c] as the real symmetric 2N x 2N [[A, B],
+ * [-B, A]], and every complex Wannier function c becomes the two real rows [Re c, Im c] and
+ * [-Im c, Re c] (the real problem has 2M rows; each complex eigenvalue appears twice). The
+ * iterates are the complex iterates; omm_energy, omm_energy_trace and omm_checkpoints report the
+ * complex problem's energy (half the real one). omm_get_C and omm_get_subspace return the real
+ * embedding (2M x 2N, 2M x 2M); omm_density_complex the complex density.
+ * omm_create_complex: N, M are the complex sizes (0 < M <= N). */
+int omm_create_complex(int64_t N, int64_t M, omm_ctx **out);
+/* Host pointers, N*N row-major each: the real and imaginary parts of H, S and (nullable) T;
+ * a null imaginary part is zero. Hermiticity is checked (OMM_E_ASYMMETRIC otherwise). */
+int omm_set_HS_complex(omm_ctx *ctx, const double *H_re, const double *H_im,
+                       const double *S_re, const double *S_im, const double *T_re,
+                       const double *T_im);
+/* C0 (M x N, host, row i = the conjugated coefficients of Wannier function i, i.e. the paper's
+ * C^H) as real and (nullable) imaginary parts; C0_re == NULL resumes. Other arguments and the
+ * return value as omm_minimize. */
+int omm_minimize_complex(omm_ctx *ctx, const double *C0_re, const double *C0_im, double eta,
+                         double tau, double tol, int max_iter);
+/* rho = 2 C^H (2I - SW) C (N x N Hermitian, host): real and imaginary parts. */
+int omm_density_complex(omm_ctx *ctx, double *rho_re, double *rho_im);
+
 /* Energies E_0, E_1, ... of the last minimize call (phase 1 then refinement), up to cap. */
 int omm_energy_trace(omm_ctx *ctx, double *buf, int cap, int *n);
 

@@ -21,6 +21,12 @@ PROTOTYPES = {
     "omm_set_resync": (ct.c_int, [_vp, ct.c_int]),
     "omm_set_flavour": (ct.c_int, [_vp, ct.c_int]),
     "omm_set_sparse": (ct.c_int, [_vp, ct.c_int]),
+    "omm_create_complex": (ct.c_int, [ct.c_int64, ct.c_int64, ct.POINTER(_vp)]),
+    "omm_set_HS_complex": (ct.c_int, [_vp, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
+                                      _c_double_p, _c_double_p]),
+    "omm_minimize_complex": (ct.c_int, [_vp, _c_double_p, _c_double_p, ct.c_double, ct.c_double,
+                                        ct.c_double, ct.c_int]),
+    "omm_density_complex": (ct.c_int, [_vp, _c_double_p, _c_double_p]),
     "omm_sparse_density": (ct.c_int, [_vp, _c_double_p]),
     "omm_checkpoints": (ct.c_int, [_vp, _c_int_p, _c_double_p, ct.c_int, _c_int_p]),
     "omm_set_stream": (ct.c_int, [_vp, _vp]),

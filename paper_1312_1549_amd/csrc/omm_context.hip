@@ -53,6 +53,10 @@ constexpr int elem_type() {
 
 struct omm_ctx {
   int64_t N = 0, M = 0;
+  // complex Hermitian problem of Nc orbitals, Mc Wannier functions held as its exact real
+  // embedding (N = 2 Nc, M = 2 Mc); energies are reported for the complex problem (E / 2)
+  bool cplx = false;
+  int64_t Nc = 0, Mc = 0;
   int device = 0;
   int mode = OMM_FP64;
   int refine = 1;
@@ -1278,7 +1282,7 @@ int omm_checkpoints(omm_ctx* c, int* iters, double* energies, int cap, int* n) {
   const int k = std::min(cap, (int)c->ck_E.size());
   for (int i = 0; i < k; ++i) {
     iters[i] = c->ck_iter[i];
-    energies[i] = c->ck_E[i];
+    energies[i] = c->ck_E[i] * (c->cplx ? 0.5 : 1.0);
   }
   if (n) *n = (int)c->ck_E.size();
   return OMM_OK;
@@ -1380,10 +1384,97 @@ int omm_minimize_device(omm_ctx* c, const double* dC0, double eta, double tau, d
   return minimize_impl(c, dC0, true, eta, tau, tol, max_iter);
 }
 
+// ---- complex Hermitian problems through the exact real embedding --------------------------
+// Row form: a complex row vector c = a + i b times X = A + i B (A symmetric, B antisymmetric)
+// is [a, b] [[A, B], [-B, A]] in real terms, and i c is the row [-b, a]. The embedded operators
+// are real symmetric of size 2 Nc; every complex Wannier function c contributes the two rows
+// [Re c, Im c] and [-Im c, Re c], so the real problem has 2 Mc rows, each complex eigenvalue
+// appears twice and the real functional is twice the complex one.
+
+int omm_create_complex(int64_t N, int64_t M, omm_ctx** out) {
+  if (!out) return OMM_E_ARG;
+  *out = nullptr;
+  if (N <= 0 || M <= 0 || M > N || N > ((int64_t)1 << 29)) return OMM_E_ARG;
+  const int r = omm_create(2 * N, 2 * M, out);
+  if (r != OMM_OK) return r;
+  (*out)->cplx = true;
+  (*out)->Nc = N;
+  (*out)->Mc = M;
+  return OMM_OK;
+}
+
+namespace {
+// [[A, B], [-B, A]] (2n x 2n) from the real and imaginary parts (n x n; im nullable = 0).
+void embed_operator(const double* re, const double* im, int64_t n, std::vector<double>& out) {
+  const int64_t n2 = 2 * n;
+  out.assign((size_t)n2 * n2, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const double a = re[i * n + j], b = im ? im[i * n + j] : 0.0;
+      out[i * n2 + j] = a;
+      out[(i + n) * n2 + j + n] = a;
+      out[i * n2 + j + n] = b;
+      out[(i + n) * n2 + j] = -b;
+    }
+}
+}  // namespace
+
+int omm_set_HS_complex(omm_ctx* c, const double* H_re, const double* H_im, const double* S_re,
+                       const double* S_im, const double* T_re, const double* T_im) {
+  if (!c) return OMM_E_ARG;
+  if (!c->cplx) return fail(c, OMM_E_STATE, "not a complex context (omm_create_complex)");
+  if (!H_re || !S_re) return fail(c, OMM_E_ARG, "the real parts of H and S are required");
+  if (!T_re && T_im) return fail(c, OMM_E_ARG, "T_im without T_re");
+  std::vector<double> H, S, T;
+  embed_operator(H_re, H_im, c->Nc, H);
+  embed_operator(S_re, S_im, c->Nc, S);
+  if (T_re) embed_operator(T_re, T_im, c->Nc, T);
+  // the embedding is symmetric exactly when the input is Hermitian: omm_set_HS checks it
+  return omm_set_HS(c, H.data(), S.data(), T_re ? T.data() : nullptr);
+}
+
+int omm_minimize_complex(omm_ctx* c, const double* C0_re, const double* C0_im, double eta,
+                         double tau, double tol, int max_iter) {
+  if (!c) return OMM_E_ARG;
+  if (!c->cplx) return fail(c, OMM_E_STATE, "not a complex context (omm_create_complex)");
+  if (!C0_re) return omm_minimize(c, nullptr, eta, tau, tol, max_iter);
+  const int64_t n = c->Nc, m = c->Mc, n2 = 2 * n;
+  std::vector<double> C((size_t)(2 * m) * n2);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const double a = C0_re[i * n + j], b = C0_im ? C0_im[i * n + j] : 0.0;
+      C[i * n2 + j] = a;
+      C[i * n2 + j + n] = b;
+      C[(i + m) * n2 + j] = -b;
+      C[(i + m) * n2 + j + n] = a;
+    }
+  return omm_minimize(c, C.data(), eta, tau, tol, max_iter);
+}
+
+int omm_density_complex(omm_ctx* c, double* rho_re, double* rho_im) {
+  if (!c || !rho_re || !rho_im) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  if (!c->cplx) return fail(c, OMM_E_STATE, "not a complex context (omm_create_complex)");
+  TRY(need_minimized(c));
+  const int64_t n = c->Nc, n2 = 2 * n;
+  TRY(dalloc(c, &c->nn_scratch, (size_t)n2 * n2));
+  TRY(ct_x_c(c, c->SW, 2.0, true, c->nn_scratch));
+  // rho = rho_hat[:n, :n] + i rho_hat[:n, n:] (the first n rows of the embedded density)
+  std::vector<double> top((size_t)n * n2);
+  HIPCHK(c, hipMemcpyAsync(top.data(), c->nn_scratch, top.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      rho_re[i * n + j] = top[i * n2 + j];
+      rho_im[i * n + j] = top[i * n2 + j + n];
+    }
+  return OMM_OK;
+}
+
 int omm_energy(omm_ctx* c, double* E) {
   if (!c || !E) return c ? fail(c, OMM_E_ARG, "E is null") : OMM_E_ARG;
   TRY(need_minimized(c));
-  *E = c->st_host->E;
+  *E = c->st_host->E * (c->cplx ? 0.5 : 1.0);
   return OMM_OK;
 }
 
@@ -1481,7 +1572,7 @@ int omm_phase_stats(omm_ctx* c, int* mixed_iters, int* fp64_iters) {
 int omm_energy_trace(omm_ctx* c, double* buf, int cap, int* n) {
   if (!c || (!buf && cap > 0)) return c ? fail(c, OMM_E_ARG, "null buffer") : OMM_E_ARG;
   const int k = (int)c->trace_host.size() < cap ? (int)c->trace_host.size() : cap;
-  for (int i = 0; i < k; ++i) buf[i] = c->trace_host[i];
+  for (int i = 0; i < k; ++i) buf[i] = c->trace_host[i] * (c->cplx ? 0.5 : 1.0);
   if (n) *n = (int)c->trace_host.size();
   return OMM_OK;
 }

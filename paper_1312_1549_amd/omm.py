@@ -236,6 +236,68 @@ class OMM:
         return buf[: n.value]
 
 
+class OMMComplex(OMM):
+    """One complex Hermitian problem (a k-point): N orbitals, M Wannier functions, held by the
+    library as its exact real embedding. Inputs are complex NumPy arrays (host)."""
+
+    def __init__(self, N: int, M: int, precision: str = "fp64", refine: bool = True,
+                 mixed_tol: Optional[float] = None, resync: Optional[int] = None,
+                 flavour: str = "dense", sparse: bool = False):
+        self._L = lib()
+        self.Nc, self.Mc = int(N), int(M)
+        self.N, self.M = 2 * self.Nc, 2 * self.Mc
+        h = ct.c_void_p()
+        r = self._L.omm_create_complex(self.Nc, self.Mc, ct.byref(h))
+        if r != OK:
+            raise OMMError(r, f"omm_create_complex(N={N}, M={M}) failed")
+        self._h = h
+        self.set_precision(precision, refine)
+        if mixed_tol is not None:
+            self._check(self._L.omm_set_mixed_tol(self._h, float(mixed_tol)))
+        if resync is not None:
+            self._check(self._L.omm_set_resync(self._h, int(resync)))
+        self.set_flavour(flavour)
+        self._check(self._L.omm_set_sparse(self._h, 1 if sparse else 0))
+        self._use_torch_stream = False
+
+    @staticmethod
+    def _parts(X, shape):
+        X = np.asarray(X)
+        if X.shape != tuple(shape):
+            raise ValueError(f"expected shape {tuple(shape)}, got {X.shape}")
+        re = np.ascontiguousarray(X.real, dtype=np.float64)
+        im = np.ascontiguousarray(X.imag, dtype=np.float64) if np.iscomplexobj(X) else None
+        return re, im
+
+    @staticmethod
+    def _p(a):
+        return None if a is None else a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+    def set_HS(self, H, S, T=None):
+        n = (self.Nc, self.Nc)
+        Hr, Hi = self._parts(H, n)
+        Sr, Si = self._parts(S, n)
+        Tr, Ti = self._parts(T, n) if T is not None else (None, None)
+        self._check(self._L.omm_set_HS_complex(self._h, self._p(Hr), self._p(Hi), self._p(Sr),
+                                               self._p(Si), self._p(Tr), self._p(Ti)))
+
+    def minimize(self, C0=None, eta: float = 0.0, tau: float = 10.0, tol: float = 1e-10,
+                 max_iter: int = 1000) -> int:
+        if C0 is None:
+            return self._check(self._L.omm_minimize_complex(self._h, None, None, float(eta),
+                                                            float(tau), float(tol), int(max_iter)))
+        Cr, Ci = self._parts(C0, (self.Mc, self.Nc))
+        return self._check(self._L.omm_minimize_complex(self._h, self._p(Cr), self._p(Ci),
+                                                        float(eta), float(tau), float(tol),
+                                                        int(max_iter)))
+
+    def density(self, out=None):
+        re = np.empty((self.Nc, self.Nc))
+        im = np.empty((self.Nc, self.Nc))
+        self._check(self._L.omm_density_complex(self._h, self._p(re), self._p(im)))
+        return re + 1j * im
+
+
 class OMMBatch:
     """Many independent systems of uneven size (FP32 products, FP64 reductions)."""
 

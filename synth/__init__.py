@@ -10,6 +10,8 @@ from .generator import (  # noqa: F401
     CONFIGS,
     System,
     batched_systems,
+    bloch_system,
+    complex_start_coefficients,
     config_system,
     lattice_positions,
     make_system,

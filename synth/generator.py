@@ -39,6 +39,8 @@ __all__ = [
     "start_coefficients",
     "perturb_hamiltonian",
     "batched_systems",
+    "bloch_system",
+    "complex_start_coefficients",
 ]
 
 
@@ -189,6 +191,77 @@ def start_coefficients(S: np.ndarray, M: int, seed: int, sigma: float = 0.01,
     Z = np.random.default_rng(seed).standard_normal(size=(M, N))
     z2 = float(np.linalg.eigvalsh(Z @ Z.T)[-1]) if M <= N else float(np.linalg.eigvalsh(Z.T @ Z)[-1])
     lam_max = _lambda_extreme(S, "LA")
+    bound = sigma * sigma * z2 * lam_max
+    scale = 1.0
+    if bound > target:
+        scale = math.floor(math.sqrt(target / bound) / _SCALE_QUANTUM) * _SCALE_QUANTUM
+    return (sigma * scale) * Z
+
+
+def bloch_system(name: str, k: float, seed: int = 0, M: Optional[int] = None) -> System:
+    """Complex Hermitian H(k), S(k), T(k) of a named workload made periodic along x.
+
+    The lattice of ``name`` (with its jitter) is repeated along x with period L = n_x a; every
+    orbital pair within r_c, including pairs with images shifted by n L (|n| <= 2), adds its
+    real amplitude (the same rule as ``make_system``) times the Bloch phase exp(i k n L). The
+    orbital-pair amplitudes are symmetric, so H(k), S(k), T(k) are Hermitian; k = 0 gives real
+    matrices with the periodic couplings. The diagonal shift that keeps S(k) positive definite
+    is chosen as in ``make_system`` from the smallest eigenvalue of S(k).
+    """
+    cfg = CONFIGS[name]
+    rng = np.random.default_rng(seed)
+    pos = lattice_positions(cfg["dims"], cfg["a"])
+    pos = pos + rng.uniform(-0.2, 0.2, size=pos.shape)
+    orbs, rc = cfg["orbs"], cfg["rc"]
+    n_atoms = pos.shape[0]
+    N = n_atoms * orbs
+    M = cfg["M"] if M is None else M
+    L = cfg["dims"][0] * cfg["a"]
+    g_abs = rng.uniform(0.5, 1.0, size=(N, N))
+    g_sign = np.where(rng.random(size=(N, N)) < 0.5, -1.0, 1.0)
+    V = rng.uniform(-1.0, 0.0, size=N)
+    g = np.triu(g_abs * g_sign, 1)
+    g = g + g.T
+    atom_of = np.repeat(np.arange(n_atoms), orbs)
+    same_orbital = np.eye(N, dtype=bool)
+    S = np.zeros((N, N), dtype=np.complex128)
+    T = np.zeros((N, N), dtype=np.complex128)
+    for n in range(-2, 3):
+        shift_vec = np.array([n * L, 0.0, 0.0])
+        diff = pos[:, None, :] - (pos[None, :, :] + shift_vec)
+        r_atom = np.sqrt(np.einsum("ijk,ijk->ij", diff, diff))
+        r = r_atom[atom_of][:, atom_of]
+        if n == 0:
+            couple = (atom_of[:, None] != atom_of[None, :]) & (r <= rc)
+        else:
+            couple = (r <= rc) & ~same_orbital
+        phase = np.exp(1j * k * n * L)
+        S += np.where(couple, np.exp(-r / 1.5) * g, 0.0) * phase
+        T += np.where(couple, 0.5 * np.exp(-r / 1.5) * g * (3.0 - 0.5 * r * r), 0.0) * phase
+    S = 0.5 * (S + S.conj().T)
+    T = 0.5 * (T + T.conj().T)
+    S[np.diag_indices(N)] = 1.0
+    lam_min = float(np.linalg.eigvalsh(S)[0])
+    shift = 0.0
+    if lam_min < 0.1:
+        shift = math.ceil((0.1 - lam_min) / _SHIFT_QUANTUM) * _SHIFT_QUANTUM
+    S[np.diag_indices(N)] += shift
+    T[np.diag_indices(N)] = 1.5 * np.real(np.diag(S))
+    H = T.copy()
+    H[np.diag_indices(N)] += V
+    return System(name=f"{name}-k{k:g}", H=H, S=S, T=T, M=M, eta=cfg["eta"], tau=cfg["tau"],
+                  shift=shift, positions=pos, orbitals_per_atom=orbs, seed=seed)
+
+
+def complex_start_coefficients(S: np.ndarray, M: int, seed: int, sigma: float = 0.01,
+                               target: float = 0.25) -> np.ndarray:
+    """Complex M x N start sigma (Z1 + i Z2) / sqrt(2), scaled so that
+    ||C0||_2^2 lambda_max(S) <= target (S Hermitian)."""
+    N = S.shape[0]
+    rng = np.random.default_rng(seed)
+    Z = (rng.standard_normal(size=(M, N)) + 1j * rng.standard_normal(size=(M, N))) / math.sqrt(2.0)
+    z2 = float(np.linalg.eigvalsh(Z @ Z.conj().T)[-1])
+    lam_max = float(np.linalg.eigvalsh(S)[-1])
     bound = sigma * sigma * z2 * lam_max
     scale = 1.0
     if bound > target:
