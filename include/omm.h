@@ -225,6 +225,19 @@ int omm_batch_iterations(omm_batch *b, int *iters /* nsys */);
 int omm_batch_get_C(omm_batch *b, int i, double *C /* host M_i*N_i */);
 const char *omm_batch_last_error(const omm_batch *b);
 
+/* k-point batches: complex Hermitian systems (N[i], M[i] the complex sizes, 0 < M <= N <= 32768)
+ * held as their exact real embeddings (see omm_create_complex) and solved together by the
+ * grouped launches above. omm_batch_energy reports the complex energies; omm_batch_get_C
+ * returns the real embedding (2M x 2N) of system i. A warm start across k passes the previous
+ * k-point's C as C0. */
+int omm_batch_create_complex(int nsys, const int64_t *N, const int64_t *M, omm_batch **out);
+int omm_batch_set_HS_complex(omm_batch *b, int i, const double *H_re, const double *H_im,
+                             const double *S_re, const double *S_im, const double *T_re,
+                             const double *T_im);
+int omm_batch_minimize_complex(omm_batch *b, const double *const *C0_re,
+                               const double *const *C0_im, const double *eta, const double *tau,
+                               double tol, int max_iter);
+
 #ifdef __cplusplus
 }
 #endif

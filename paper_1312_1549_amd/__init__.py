@@ -7,6 +7,7 @@ The minimization runs in the HIP kernels of ``libomm.so`` (built in-tree by
 from .omm import (  # noqa: F401
     OMM,
     OMMBatch,
+    OMMBatchComplex,
     OMMComplex,
     OMMError,
     PRECISIONS,

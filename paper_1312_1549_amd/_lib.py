@@ -27,6 +27,11 @@ PROTOTYPES = {
     "omm_minimize_complex": (ct.c_int, [_vp, _c_double_p, _c_double_p, ct.c_double, ct.c_double,
                                         ct.c_double, ct.c_int]),
     "omm_density_complex": (ct.c_int, [_vp, _c_double_p, _c_double_p]),
+    "omm_batch_create_complex": (ct.c_int, [ct.c_int, _c_i64_p, _c_i64_p, ct.POINTER(_vp)]),
+    "omm_batch_set_HS_complex": (ct.c_int, [_vp, ct.c_int, _c_double_p, _c_double_p,
+                                            _c_double_p, _c_double_p, _c_double_p, _c_double_p]),
+    "omm_batch_minimize_complex": (ct.c_int, [_vp, ct.POINTER(_vp), ct.POINTER(_vp), _c_double_p,
+                                              _c_double_p, ct.c_double, ct.c_int]),
     "omm_sparse_density": (ct.c_int, [_vp, _c_double_p]),
     "omm_checkpoints": (ct.c_int, [_vp, _c_int_p, _c_double_p, ct.c_int, _c_int_p]),
     "omm_set_stream": (ct.c_int, [_vp, _vp]),

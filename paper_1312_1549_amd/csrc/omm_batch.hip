@@ -65,6 +65,9 @@ struct omm_batch {
   std::vector<int> iters;
   std::vector<double> E;
   std::string err;
+  // complex Hermitian systems (k-points) held as their real embeddings (sizes 2N, 2M)
+  bool cplx = false;
+  std::vector<int64_t> Nc, Mc;
 };
 
 namespace {
@@ -523,8 +526,57 @@ int omm_batch_minimize(omm_batch* b, const double* const* C0, const double* eta,
 
 int omm_batch_energy(omm_batch* b, double* E) {
   if (!b || !E) return OMM_E_ARG;
-  for (size_t i = 0; i < b->E.size(); ++i) E[i] = b->E[i];
+  for (size_t i = 0; i < b->E.size(); ++i) E[i] = b->E[i] * (b->cplx ? 0.5 : 1.0);
   return OMM_OK;
+}
+
+int omm_batch_create_complex(int nsys, const int64_t* N, const int64_t* M, omm_batch** out) {
+  if (!out) return OMM_E_ARG;
+  *out = nullptr;
+  if (nsys <= 0 || !N || !M) return OMM_E_ARG;
+  std::vector<int64_t> N2(nsys), M2(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    if (N[i] <= 0 || M[i] <= 0 || M[i] > N[i] || N[i] > (1 << 15)) return OMM_E_ARG;
+    N2[i] = 2 * N[i];
+    M2[i] = 2 * M[i];
+  }
+  const int r = omm_batch_create(nsys, N2.data(), M2.data(), out);
+  if (r != OMM_OK) return r;
+  (*out)->cplx = true;
+  (*out)->Nc.assign(N, N + nsys);
+  (*out)->Mc.assign(M, M + nsys);
+  return OMM_OK;
+}
+
+int omm_batch_set_HS_complex(omm_batch* b, int i, const double* H_re, const double* H_im,
+                             const double* S_re, const double* S_im, const double* T_re,
+                             const double* T_im) {
+  if (!b) return OMM_E_ARG;
+  if (!b->cplx) return bfail(b, OMM_E_STATE, "not a complex batch (omm_batch_create_complex)");
+  if (i < 0 || i >= (int)b->sys.size()) return bfail(b, OMM_E_ARG, "system index out of range");
+  if (!H_re || !S_re) return bfail(b, OMM_E_ARG, "the real parts of H and S are required");
+  if (!T_re && T_im) return bfail(b, OMM_E_ARG, "T_im without T_re");
+  std::vector<double> H, S, T;
+  embed_operator(H_re, H_im, b->Nc[i], H);
+  embed_operator(S_re, S_im, b->Nc[i], S);
+  if (T_re) embed_operator(T_re, T_im, b->Nc[i], T);
+  return omm_batch_set_HS(b, i, H.data(), S.data(), T_re ? T.data() : nullptr);
+}
+
+int omm_batch_minimize_complex(omm_batch* b, const double* const* C0_re,
+                               const double* const* C0_im, const double* eta, const double* tau,
+                               double tol, int max_iter) {
+  if (!b) return OMM_E_ARG;
+  if (!b->cplx) return bfail(b, OMM_E_STATE, "not a complex batch (omm_batch_create_complex)");
+  const int n = (int)b->sys.size();
+  std::vector<std::vector<double>> C(n);
+  std::vector<const double*> ptr(n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    if (!C0_re || !C0_re[i]) continue;
+    embed_rows(C0_re[i], C0_im ? C0_im[i] : nullptr, b->Mc[i], b->Nc[i], C[i]);
+    ptr[i] = C[i].data();
+  }
+  return omm_batch_minimize(b, ptr.data(), eta, tau, tol, max_iter);
 }
 
 int omm_batch_iterations(omm_batch* b, int* iters) {

@@ -1175,6 +1175,35 @@ int need_minimized(omm_ctx* c) {
 
 }  // namespace
 
+// [[A, B], [-B, A]] (2n x 2n) from the real and imaginary parts (n x n; im nullable = 0).
+void omm::embed_operator(const double* re, const double* im, int64_t n, std::vector<double>& out) {
+  const int64_t n2 = 2 * n;
+  out.assign((size_t)n2 * n2, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const double a = re[i * n + j], b = im ? im[i * n + j] : 0.0;
+      out[i * n2 + j] = a;
+      out[(i + n) * n2 + j + n] = a;
+      out[i * n2 + j + n] = b;
+      out[(i + n) * n2 + j] = -b;
+    }
+}
+
+// Rows [Re c_i, Im c_i] (i < m) and [-Im c_i, Re c_i] (2m x 2n) of the complex m x n C.
+void omm::embed_rows(const double* re, const double* im, int64_t m, int64_t n, std::vector<double>& out) {
+  const int64_t n2 = 2 * n;
+  out.assign((size_t)(2 * m) * n2, 0.0);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const double a = re[i * n + j], b = im ? im[i * n + j] : 0.0;
+      out[i * n2 + j] = a;
+      out[i * n2 + j + n] = b;
+      out[(i + m) * n2 + j] = -b;
+      out[(i + m) * n2 + j + n] = a;
+    }
+}
+
+
 extern "C" {
 
 int omm_create(int64_t N, int64_t M, omm_ctx** out) {
@@ -1403,22 +1432,6 @@ int omm_create_complex(int64_t N, int64_t M, omm_ctx** out) {
   return OMM_OK;
 }
 
-namespace {
-// [[A, B], [-B, A]] (2n x 2n) from the real and imaginary parts (n x n; im nullable = 0).
-void embed_operator(const double* re, const double* im, int64_t n, std::vector<double>& out) {
-  const int64_t n2 = 2 * n;
-  out.assign((size_t)n2 * n2, 0.0);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t j = 0; j < n; ++j) {
-      const double a = re[i * n + j], b = im ? im[i * n + j] : 0.0;
-      out[i * n2 + j] = a;
-      out[(i + n) * n2 + j + n] = a;
-      out[i * n2 + j + n] = b;
-      out[(i + n) * n2 + j] = -b;
-    }
-}
-}  // namespace
-
 int omm_set_HS_complex(omm_ctx* c, const double* H_re, const double* H_im, const double* S_re,
                        const double* S_im, const double* T_re, const double* T_im) {
   if (!c) return OMM_E_ARG;
@@ -1438,16 +1451,8 @@ int omm_minimize_complex(omm_ctx* c, const double* C0_re, const double* C0_im, d
   if (!c) return OMM_E_ARG;
   if (!c->cplx) return fail(c, OMM_E_STATE, "not a complex context (omm_create_complex)");
   if (!C0_re) return omm_minimize(c, nullptr, eta, tau, tol, max_iter);
-  const int64_t n = c->Nc, m = c->Mc, n2 = 2 * n;
-  std::vector<double> C((size_t)(2 * m) * n2);
-  for (int64_t i = 0; i < m; ++i)
-    for (int64_t j = 0; j < n; ++j) {
-      const double a = C0_re[i * n + j], b = C0_im ? C0_im[i * n + j] : 0.0;
-      C[i * n2 + j] = a;
-      C[i * n2 + j + n] = b;
-      C[(i + m) * n2 + j] = -b;
-      C[(i + m) * n2 + j + n] = a;
-    }
+  std::vector<double> C;
+  embed_rows(C0_re, C0_im, c->Mc, c->Nc, C);
   return omm_minimize(c, C.data(), eta, tau, tol, max_iter);
 }
 

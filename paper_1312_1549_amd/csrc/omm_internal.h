@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace omm {
 
 // Device-resident scalars of one minimization. Every iteration kernel reads `done` first and
@@ -80,6 +82,11 @@ constexpr int SPARSE_BN = 256, SPARSE_BK = 32;
 // flags[t * nkb + kb] = 1 iff some B[r][k] != 0 with r in column tile t and k in K block kb
 // (B is n x n row-major; nkb = ceil(n / SPARSE_BK)).
 hipError_t block_pattern(const double* B, int64_t n, unsigned char* flags, hipStream_t s);
+// Exact real embedding of complex Hermitian problems (host side): the operator X = re + i im
+// (n x n) becomes [[re, im], [-im, re]] (2n x 2n, acting on rows [Re c, Im c]); the complex
+// m x n row matrix C becomes the 2m x 2n rows [Re c_i, Im c_i] and [-Im c_i, Re c_i].
+void embed_operator(const double* re, const double* im, int64_t n, std::vector<double>& out);
+void embed_rows(const double* re, const double* im, int64_t m, int64_t n, std::vector<double>& out);
 int gemm_num_tiles();
 int gemm_grouped_num_tiles();
 bool gemm_supported(const GemmDesc& d);

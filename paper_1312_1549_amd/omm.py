@@ -367,6 +367,57 @@ class OMMBatch:
         return out
 
 
+class OMMBatchComplex(OMMBatch):
+    """k-point batch: complex Hermitian systems (complex sizes Ns, Ms) solved together through
+    their real embeddings. Inputs are complex NumPy arrays."""
+
+    def __init__(self, Ns: Sequence[int], Ms: Sequence[int]):
+        self._L = lib()
+        self.Nc = [int(n) for n in Ns]
+        self.Mc = [int(m) for m in Ms]
+        self.Ns = [2 * n for n in self.Nc]
+        self.Ms = [2 * m for m in self.Mc]
+        k = len(self.Nc)
+        h = ct.c_void_p()
+        r = self._L.omm_batch_create_complex(k, (ct.c_int64 * k)(*self.Nc),
+                                             (ct.c_int64 * k)(*self.Mc), ct.byref(h))
+        if r != OK:
+            raise OMMError(r, "omm_batch_create_complex failed")
+        self._h = h
+
+    def set_HS(self, i: int, H, S, T=None):
+        n = (self.Nc[i], self.Nc[i])
+        parts = [OMMComplex._parts(X, n) if X is not None else (None, None) for X in (H, S, T)]
+        p = OMMComplex._p
+        self._check(self._L.omm_batch_set_HS_complex(self._h, i, p(parts[0][0]), p(parts[0][1]),
+                                                     p(parts[1][0]), p(parts[1][1]),
+                                                     p(parts[2][0]), p(parts[2][1])))
+
+    def minimize(self, C0s, etas, taus, tol: float, max_iter: int) -> int:
+        k = len(self.Nc)
+        keep = []
+        re = (ct.c_void_p * k)()
+        im = (ct.c_void_p * k)()
+        for i in range(k):
+            if C0s is None or C0s[i] is None:
+                re[i] = im[i] = None
+                continue
+            r, j = OMMComplex._parts(C0s[i], (self.Mc[i], self.Nc[i]))
+            keep += [r, j]
+            re[i] = r.ctypes.data
+            im[i] = j.ctypes.data if j is not None else None
+        e = (ct.c_double * k)(*[float(x) for x in etas])
+        t = (ct.c_double * k)(*[float(x) for x in taus])
+        return self._check(self._L.omm_batch_minimize_complex(self._h, re, im, e, t, float(tol),
+                                                              int(max_iter)))
+
+    def get_C_complex(self, i: int) -> np.ndarray:
+        """The complex Wannier functions held in the first M rows of system i's embedding."""
+        C = self.get_C(i)
+        m, n = self.Mc[i], self.Nc[i]
+        return C[:m, :n] + 1j * C[:m, n:]
+
+
 def _energy_function():
     import torch
 

@@ -51,6 +51,13 @@ def test_argument_errors_need_no_gpu(libomm):
     assert libomm.omm_create(10, 2, None) == -1
     assert libomm.omm_destroy(None) == -1
     assert libomm.omm_last_error(None) == b"null context"
+    N = (ct.c_int64 * 2)(64, 64)
+    M = (ct.c_int64 * 2)(8, 65)
+    assert libomm.omm_batch_create_complex(2, N, M, ct.byref(h)) == -1  # M > N
+    assert libomm.omm_batch_create_complex(0, N, M, ct.byref(h)) == -1
+    big = (ct.c_int64 * 1)(1 << 16)
+    assert libomm.omm_batch_create_complex(1, big, M, ct.byref(h)) == -1
+    assert libomm.omm_create_complex(10, 11, ct.byref(h)) == -1
 
 
 def test_no_silent_cpu_fallback(libomm):
