@@ -725,6 +725,11 @@ int prof_collect(omm_ctx* c) {
   return OMM_OK;
 }
 
+bool fuse_enabled() {
+  const char* e = getenv("OMM_FUSE");
+  return !(e && e[0] == '0');
+}
+
 // One line search (the stage sequence in the header comment of this file). In BF16x3 mode every
 // GEMM operand is split into bf16 hi/lo planes once, right after it is produced.
 template <typename T>
@@ -733,6 +738,9 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   const int M = (int)c->M, N = (int)c->N;
   const int64_t mn = (int64_t)M * N;
   const bool bf = compute == CBF16X3;
+  // BF16: the operand planes of G, HD, SD come from the GEMM epilogues and those of HC, SC from
+  // the update kernel; OMM_FUSE=0 splits them in separate passes instead (same values)
+  const bool fuse = bf && fuse_enabled();
   const int et = elem_type<T>();
   const int ot = bf ? T_BF16P : et;  // operand element type of the GEMMs
   const int* done = &c->st->done;
@@ -754,6 +762,10 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     op.A[1] = a2.p; op.Alo[1] = a2.lo; op.lda[1] = M;
     op.B[1] = b2.p; op.Blo[1] = b2.lo; op.ldb[1] = bf ? M : N;
     op.K[1] = M;
+    if (fuse && c->p_kind > 0) {  // G's planes for the preconditioner product, from the epilogue
+      op.Chi = c->G_p.hi;
+      op.Clo = c->G_p.lo;
+    }
     TRY(gemm(c, d, &op, 1, done));
   }
   TRY(prof_mark(c));
@@ -764,7 +776,7 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   const int cP = bf ? CBF16X2B : compute, cD = bf ? CBF16X2A : compute;
   T* PG = G;
   if (c->p_kind > 0) {
-    if (bf) TRY(split(c, G, c->G_p, mn));
+    if (bf && !fuse) TRY(split(c, G, c->G_p, mn));
     GemmDesc d{cP, ot, ot, et, et, KC, KC, 0, 1};
     GemmOp op = make_op2(M, N, N, bf ? pl(c->G_p) : dn(G), N, bf ? pl(c->P_p) : dn(P), N, w.PG, N);
     TRY(gemm(c, d, &op, 1, done));
@@ -788,10 +800,16 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
         ops[i].kidx = c->kl_idx[i];
       }
     }
+    if (fuse) {  // the projection stage's operand planes, from the epilogue
+      ops[0].Chi = c->HD_p.hi;
+      ops[0].Clo = c->HD_p.lo;
+      ops[1].Chi = c->SD_p.hi;
+      ops[1].Clo = c->SD_p.lo;
+    }
     TRY(gemm(c, d, ops, sid ? 1 : 2, done));
   }
   TRY(prof_mark(c));
-  if (bf) {  // the projection stage's operand planes (D's lo plane stays zero)
+  if (bf && !fuse) {  // the projection stage's operand planes (D's lo plane stays zero)
     TRY(split(c, w.HD, c->HD_p, mn));
     if (!sid) TRY(split(c, w.SD, c->SD_p, mn));
   }
@@ -808,8 +826,15 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   HIPCHK(c, line_search(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
                         c->stream));
   TRY(prof_mark(c));
-  HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, mn, c->st, c->stream));
-  if (bf) TRY(split_state(c, w.HC, w.SC));
+  if (fuse) {  // with the planes of the new HC, SC and of their transposes
+    const StatePlanes sp{c->HC_p.hi,  c->HC_p.lo,  c->SC_p.hi,  c->SC_p.lo,
+                         c->HCt_p.hi, c->HCt_p.lo, c->SCt_p.hi, c->SCt_p.lo};
+    HIPCHK(c, update_coefficients_split<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, M, N, sp, c->st,
+                                           c->stream));
+  } else {
+    HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, mn, c->st, c->stream));
+    if (bf) TRY(split_state(c, w.HC, w.SC));
+  }
   HIPCHK(c, update_subspace(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
                             trace, c->stream));
   TRY(prof_mark(c));

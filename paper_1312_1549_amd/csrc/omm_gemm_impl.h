@@ -362,6 +362,19 @@ struct AccT<CF64> {
   typedef d4 type;
 };
 
+// Stores output element e = row * ldc + col and, if the op asks for them, its bf16 planes.
+template <typename TC>
+__device__ __forceinline__ void store_out(const GemmOp& op, int64_t e, double v) {
+  const TC c = (TC)v;
+  static_cast<TC*>(op.C)[e] = c;
+  if (op.Chi) {
+    const double w = (double)c;
+    const unsigned short h = bf16_rne((float)w);
+    static_cast<unsigned short*>(op.Chi)[e] = h;
+    static_cast<unsigned short*>(op.Clo)[e] = bf16_rne((float)(w - (double)bf16_val(h)));
+  }
+}
+
 // Epilogue of one wave's TM x TN blocks at (r0, c0): C = alpha acc + beta X, or the FP64 split-K
 // partial at ws[(sp * nops + z) * M * N + ...].
 template <int MODE, typename TC, typename TX, int TM, int TN, typename acc_t>
@@ -384,7 +397,7 @@ __device__ __forceinline__ void store_acc(const GemmOp& op, const acc_t (&acc)[T
           } else {
             double v = op.alpha * s;
             if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
-            static_cast<TC*>(op.C)[(int64_t)row * op.ldc + col] = (TC)v;
+            store_out<TC>(op, (int64_t)row * op.ldc + col, v);
           }
         }
       }
@@ -553,7 +566,9 @@ __device__ __forceinline__ void wait_vm_lgkm0() {
 
 constexpr int DMA_TM = 8, DMA_TN = 4;  // 16 x 16 blocks per wave (wave grid 2 x 4)
 template <int KIND, typename TC>
-struct DmaUser {};
+struct DmaUser {
+  static constexpr int kind = KIND;  // 0: one tile per workgroup, 1: stream-K
+};
 
 // Accumulates the K range [g0, g1) (concatenated over the segments) of tile (tm, tn) into acc.
 // USER (the calling kernel and its output type) only makes each kernel instantiate its own copy:
@@ -660,24 +675,71 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
         return __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(
                                            base + lds_off<true, RS>(r, kof)));
       };
-      bf8 bh[TN], bl[TN];
+      // Software pipeline over pairs of 16-row blocks: the A fragments of pair p + 1 are read
+      // from LDS while the MFMAs of pair p run, so a wave waits on LDS once per stage (for its
+      // B fragments and first pair) instead of once per pair.
+      constexpr int PAIR = 2, NPAIR = TM / PAIR, NAR = ONE_A ? 1 : 2;
+      constexpr int NPROD = (ONE_A || ONE_B) ? 2 : 3, NBR = TN * (ONE_B ? 1 : 2);
+      static_assert(TM % PAIR == 0, "row blocks come in pairs");
+      bf8 ah[2][PAIR], al[2][PAIR], bh[TN], bl[TN];
+      auto load_pair = [&](int p) {
+#pragma unroll
+        for (int q = 0; q < PAIR; ++q) {
+          const int r = wm * TM * 16 + (p * PAIR + q) * 16 + (lane & 15);
+          ah[p & 1][q] = frag(a0, r);
+          al[p & 1][q] = ONE_A ? ah[p & 1][q] : frag(a1, r);
+        }
+      };
+      auto mfma_row = [&](int p, int q) {
+        const int i = p * PAIR + q;
+        const bf8 h = ah[p & 1][q], l = al[p & 1][q];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          if constexpr (!ONE_A)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bh[j], acc[i][j], 0, 0, 0);
+          if constexpr (!ONE_B)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bh[j], acc[i][j], 0, 0, 0);
+        }
+      };
+      // the stream-K kernel with three products has no registers to spare for the next pair
+      constexpr bool PIPE = !(NPROD == 3 && USER::kind == 1);
+      if constexpr (PIPE) load_pair(0);
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int r = wn * TN * 16 + j * 16 + (lane & 15);
         bh[j] = frag(b0, r);
         bl[j] = ONE_B ? bh[j] : frag(b1, r);
       }
+      if constexpr (PIPE) {
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int r = wm * TM * 16 + i * 16 + (lane & 15);
-        const bf8 ah = frag(a0, r), al = ONE_A ? ah : frag(a1, r);
+        for (int p = 0; p < NPAIR; ++p) {
+          mfma_row(p, 0);
+          if (p + 1 < NPAIR) load_pair(p + 1);
+          mfma_row(p, 1);
+        }
+        // instruction groups for the scheduler: [reads of pair 0 and B] then, per pair p,
+        // [MFMAs of its first row block] [reads of pair p + 1] [MFMAs of its second row block]
+        __builtin_amdgcn_sched_group_barrier(0x100, PAIR * NAR + NBR, 0);
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          if constexpr (!ONE_A)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-          if constexpr (!ONE_B)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+        for (int p = 0; p < NPAIR; ++p) {
+          __builtin_amdgcn_sched_group_barrier(0x008, TN * NPROD, 0);
+          if (p + 1 < NPAIR) __builtin_amdgcn_sched_group_barrier(0x100, PAIR * NAR, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, TN * NPROD, 0);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const int r = wm * TM * 16 + i * 16 + (lane & 15);
+          const bf8 h = frag(a0, r), l = ONE_A ? h : frag(a1, r);
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            if constexpr (!ONE_A)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bh[j], acc[i][j], 0, 0, 0);
+            if constexpr (!ONE_B)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bh[j], acc[i][j], 0, 0, 0);
+          }
         }
       }
     }
@@ -833,7 +895,7 @@ __global__ __launch_bounds__(256) void gemm_sk_fixup(GemmBatch batch, const int*
     if (row < op.M && col < op.N) {
       double v = op.alpha * sum;
       if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
-      static_cast<TC*>(op.C)[(int64_t)row * op.ldc + col] = (TC)v;
+      store_out<TC>(op, (int64_t)row * op.ldc + col, v);
     }
   }
 }

@@ -59,6 +59,10 @@ struct GemmOp {
   // zeros, so the result equals the dense product (up to the sign of zero).
   const int* kptr;
   const int* kidx;
+  // Optional bf16 planes of the output (nullable; same layout and leading dimension as C):
+  // Chi = bf16(c), Clo = bf16(c - Chi) of each stored element c, for the next product's operand.
+  void* Chi;
+  void* Clo;
 };
 
 struct GemmDesc {
@@ -139,6 +143,18 @@ hipError_t line_search(const double* HW, const double* SW, const double* H1, con
 template <typename T>
 hipError_t update_coefficients(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
                                const DevState* st, hipStream_t s);
+
+// bf16 hi/lo planes of HC and SC (rows x cols) and of their transposes (cols x rows).
+struct StatePlanes {
+  unsigned short *hc_hi, *hc_lo, *sc_hi, *sc_lo;
+  unsigned short *hct_hi, *hct_lo, *sct_hi, *sct_lo;
+};
+// update_coefficients (rows x cols arrays) fused with the splits of the new HC and SC into `p`
+// (the same values split_bf16 and split_bf16_t would write).
+template <typename T>
+hipError_t update_coefficients_split(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD,
+                                     int rows, int cols, const StatePlanes& p, const DevState* st,
+                                     hipStream_t s);
 
 hipError_t update_subspace(double* HW, double* SW, const double* H1, const double* S1,
                            const double* H2, const double* S2, int M, double* partials,

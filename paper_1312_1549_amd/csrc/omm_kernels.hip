@@ -479,6 +479,50 @@ __global__ void k_update_mn(T* C, const T* D, T* HC, const T* HD, T* SC, const T
   b_update_mn(C, D, HC, HD, SC, SD, n, st, blockIdx.x, gridDim.x);
 }
 
+__device__ __forceinline__ void split_store(double v, unsigned short* hi, unsigned short* lo,
+                                            int64_t e) {
+  const unsigned short hb = bf16_bits((float)v);
+  hi[e] = hb;
+  lo[e] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+}
+
+// Eq. 16 for C, HC, SC (rows x cols) with the bf16 planes of the new HC and SC, row-major and
+// transposed (through a 32 x 33 LDS tile), one 32 x 32 tile per block.
+template <typename T>
+__global__ void k_update_split_mn(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD,
+                                  int rows, int cols, StatePlanes p, const DevState* st) {
+  if (st->done) return;
+  __shared__ T th[32][33], ts[32][33];
+  const double x = st->x;
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int gr = r0 + r, gc = c0 + tx;
+    T h = (T)0, v = (T)0;
+    if (gr < rows && gc < cols) {
+      const int64_t e = (int64_t)gr * cols + gc;
+      C[e] = (T)((double)C[e] + x * (double)D[e]);
+      h = (T)((double)HC[e] + x * (double)HD[e]);
+      v = (T)((double)SC[e] + x * (double)SD[e]);
+      HC[e] = h;
+      SC[e] = v;
+      split_store((double)h, p.hc_hi, p.hc_lo, e);
+      split_store((double)v, p.sc_hi, p.sc_lo, e);
+    }
+    th[r][tx] = h;
+    ts[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int oc = c0 + r, orow = r0 + tx;  // output row oc (a source column), column orow
+    if (oc < cols && orow < rows) {
+      const int64_t o = (int64_t)oc * rows + orow;
+      split_store((double)th[tx][r], p.hct_hi, p.hct_lo, o);
+      split_store((double)ts[tx][r], p.sct_hi, p.sct_lo, o);
+    }
+  }
+}
+
 // HW += x (H' + H'^T) + x^2 H'', SW likewise; partial sums of Tr HW, <SW, HW>, Tr SW.
 __device__ __forceinline__ void b_update_mm(double* HW, double* SW, const double* H1, const double* S1,
                             const double* H2, const double* S2, int M, double* partials,
@@ -750,6 +794,24 @@ template hipError_t update_coefficients<double>(double*, const double*, double*,
 template hipError_t update_coefficients<float>(float*, const float*, float*, const float*, float*,
                                                const float*, int64_t, const DevState*,
                                                hipStream_t);
+
+template <typename T>
+hipError_t update_coefficients_split(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD,
+                                     int rows, int cols, const StatePlanes& p, const DevState* st,
+                                     hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update_split_mn<T>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0, s,
+                     C, D, HC, HD, SC, SD, rows, cols, p, st);
+  return hipGetLastError();
+}
+template hipError_t update_coefficients_split<double>(double*, const double*, double*,
+                                                      const double*, double*, const double*, int,
+                                                      int, const StatePlanes&, const DevState*,
+                                                      hipStream_t);
+template hipError_t update_coefficients_split<float>(float*, const float*, float*, const float*,
+                                                     float*, const float*, int, int,
+                                                     const StatePlanes&, const DevState*,
+                                                     hipStream_t);
 
 hipError_t update_subspace(double* HW, double* SW, const double* H1, const double* S1,
                            const double* H2, const double* S2, int M, double* partials,

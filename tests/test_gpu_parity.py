@@ -256,6 +256,34 @@ def test_stream_k_tile_converges_like_direct_tile(lib_ok, M, monkeypatch):
     assert abs(E["6"] - E_ref) <= 1e-9 * abs(E_ref)
 
 
+@pytest.mark.parametrize("tile,refine", [("4", True), ("5", True), ("5", False), ("6", True),
+                                         (None, True)])
+def test_fused_planes_match_separate_splits(lib_ok, c2, tile, refine, monkeypatch):
+    """The bf16 planes written by the GEMM epilogues (G, HD, SD: register tile, direct-to-LDS
+    tile, stream-K fix-up, or whatever the autotuner picks) and by the fused update kernel (HC,
+    SC and their transposes) equal those of the separate split passes (OMM_FUSE=0): energy
+    trajectories and C agree bit for bit."""
+    if tile is None:
+        s, C0, _ = c2
+    else:
+        rng = np.random.default_rng(60)
+        pos = lattice_positions((5, 5, 2), 2.5)
+        pos = pos + rng.uniform(-0.2, 0.2, size=pos.shape)
+        s = make_system(pos, 4, 6.0, 37, rng, name="fuse", eta=0.5, tau=10.0, seed=60)
+        C0 = start_coefficients(s.S, s.M, 61)
+        monkeypatch.setenv("OMM_TILE", tile)
+    _say(f"fused vs separate planes N={s.N} M={s.M} tile={tile} refine={refine}")
+    out = []
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("OMM_FUSE", fuse)
+        solver, _ = _run(lib_ok, s, C0, 0.5, 10.0, 0.0, 40, precision="bf16x3", refine=refine)
+        out.append((solver.energy_trace(), solver.get_C()))
+        solver.close()
+    assert len(out[0][0]) == 41
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_fully_occupied_limit(lib_ok):
     """M = N: every eigenvector is occupied; with eta above the whole spectrum the minimum is
     2 sum_i (eps_i - eta) and SW = I (C^T C = S^-1 in row form)."""
