@@ -40,6 +40,7 @@ struct Work {
 struct Plane {
   unsigned short* hi = nullptr;
   unsigned short* lo = nullptr;
+  int64_t ld = 0;  // row length (elements)
 };
 
 constexpr int NSTAGE = 7;  // gradient, PG, PR+direction, [HD|SD], projections, line search, updates
@@ -194,8 +195,15 @@ void free_work(Work<T>& w) {
   dfree(w.HD); dfree(w.SD);
 }
 
-int alloc_plane(omm_ctx* c, Plane& p, size_t n) {
+// Row length of a bf16 plane with `cols` columns: a multiple of 64 elements, so that every row
+// starts on a 128-byte line and each 64-byte K chunk the GEMM tiles fetch is one aligned request
+// (an unaligned chunk straddles two).
+int64_t plane_ld(int64_t cols) { return (cols + 63) / 64 * 64; }
+
+int alloc_plane(omm_ctx* c, Plane& p, int64_t rows, int64_t cols) {
   if (p.hi) return OMM_OK;
+  p.ld = plane_ld(cols);
+  const size_t n = (size_t)rows * p.ld;
   TRY(dalloc(c, &p.hi, n));
   TRY(dalloc(c, &p.lo, n));
   // never read before written; zeroed so that a missed split could not depend on stale memory
@@ -531,13 +539,14 @@ int prepare_shift(omm_ctx* c, double eta) {
   }
   if (c->mode == OMM_BF16X3) {
     if (!c->hsp_valid) {
-      TRY(alloc_plane(c, c->Hs_p, nn));
-      HIPCHK(c, split_bf16(c->Hs, c->Hs_p.hi, c->Hs_p.lo, (int64_t)nn, nullptr, c->stream));
+      TRY(alloc_plane(c, c->Hs_p, c->N, c->N));
+      HIPCHK(c, split_bf16(c->Hs, c->Hs_p.hi, c->Hs_p.lo, c->N, c->N, c->Hs_p.ld, nullptr,
+                           c->stream));
       c->hsp_valid = true;
     }
     if (!c->sp_valid && !red) {
-      TRY(alloc_plane(c, c->S_p, nn));
-      HIPCHK(c, split_bf16(c->S, c->S_p.hi, c->S_p.lo, (int64_t)nn, nullptr, c->stream));
+      TRY(alloc_plane(c, c->S_p, c->N, c->N));
+      HIPCHK(c, split_bf16(c->S, c->S_p.hi, c->S_p.lo, c->N, c->N, c->S_p.ld, nullptr, c->stream));
       c->sp_valid = true;
     }
     if (sparse_products(c)) {
@@ -586,8 +595,8 @@ int prepare_precon(omm_ctx* c, double tau) {
     c->pp_valid = false;
   }
   if (kind > 0 && c->mode == OMM_BF16X3 && !c->pp_valid) {
-    TRY(alloc_plane(c, c->P_p, nn));
-    HIPCHK(c, split_bf16(c->P, c->P_p.hi, c->P_p.lo, (int64_t)nn, nullptr, c->stream));
+    TRY(alloc_plane(c, c->P_p, c->N, c->N));
+    HIPCHK(c, split_bf16(c->P, c->P_p.hi, c->P_p.lo, c->N, c->N, c->P_p.ld, nullptr, c->stream));
     c->pp_valid = true;
   }
   if (kind > 0 && c->mode == OMM_FP32 && !c->p32_valid) {
@@ -617,38 +626,47 @@ int alloc_common(omm_ctx* c) {
   return OMM_OK;
 }
 
-// Operand of a GEMM: plain pointer, or the hi/lo planes for BF16x3.
+// Operand of a GEMM: plain pointer, or the hi/lo planes for BF16x3; ld = row length.
 struct Opnd {
   const void* p;
   const void* lo;
+  int64_t ld;
 };
 
-GemmOp make_op2(int M, int N, int K, Opnd A, int64_t lda, Opnd B, int64_t ldb, void* C, int64_t ldc,
-                double alpha = 1.0, const void* X = nullptr, int64_t ldx = 0, double beta = 0.0) {
-  GemmOp op = make_op(M, N, K, A.p, lda, B.p, ldb, C, ldc, alpha, X, ldx, beta);
+GemmOp make_op2(int M, int N, int K, Opnd A, Opnd B, void* C, int64_t ldc, double alpha = 1.0,
+                const void* X = nullptr, int64_t ldx = 0, double beta = 0.0) {
+  GemmOp op = make_op(M, N, K, A.p, A.ld, B.p, B.ld, C, ldc, alpha, X, ldx, beta);
   op.Alo[0] = A.lo;
   op.Blo[0] = B.lo;
   return op;
 }
 
-Opnd pl(const Plane& p) { return {p.hi, p.lo}; }
+Opnd pl(const Plane& p) { return {p.hi, p.lo, p.ld}; }
 template <typename T>
-Opnd dn(const T* p) { return {p, nullptr}; }
+Opnd dn(const T* p, int64_t ld) { return {p, nullptr, ld}; }
 
-// Planes for the per-iteration BF16x3 operands (M x N and M x M).
+// The output planes an op's epilogue writes (the next product's operand).
+void out_planes(GemmOp& op, const Plane& p) {
+  op.Chi = p.hi;
+  op.Clo = p.lo;
+  op.ldp = p.ld;
+}
+
+// Planes for the per-iteration BF16x3 operands (M x N, N x M and M x M).
 int alloc_iter_planes(omm_ctx* c) {
-  const size_t mn = (size_t)c->M * c->N, mm = (size_t)c->M * c->M;
-  for (Plane* p : {&c->C_p, &c->HC_p, &c->SC_p, &c->G_p, &c->D_p, &c->HD_p, &c->SD_p, &c->HCt_p,
-                   &c->SCt_p})
-    TRY(alloc_plane(c, *p, mn));
-  TRY(alloc_plane(c, c->HW_p, mm));
-  TRY(alloc_plane(c, c->SW_p, mm));
+  for (Plane* p : {&c->C_p, &c->HC_p, &c->SC_p, &c->G_p, &c->D_p, &c->HD_p, &c->SD_p})
+    TRY(alloc_plane(c, *p, c->M, c->N));
+  TRY(alloc_plane(c, c->HCt_p, c->N, c->M));
+  TRY(alloc_plane(c, c->SCt_p, c->N, c->M));
+  TRY(alloc_plane(c, c->HW_p, c->M, c->M));
+  TRY(alloc_plane(c, c->SW_p, c->M, c->M));
   return OMM_OK;
 }
 
+// Planes of a rows x cols array.
 template <typename T>
-int split(omm_ctx* c, const T* src, Plane& p, int64_t n, bool check_done = true) {
-  HIPCHK(c, split_bf16(src, p.hi, p.lo, n, check_done ? c->st : nullptr, c->stream));
+int split(omm_ctx* c, const T* src, Plane& p, int64_t rows, int64_t cols, bool check_done = true) {
+  HIPCHK(c, split_bf16(src, p.hi, p.lo, rows, cols, p.ld, check_done ? c->st : nullptr, c->stream));
   return OMM_OK;
 }
 
@@ -657,10 +675,10 @@ template <typename T>
 int split_state(omm_ctx* c, const T* HC, const T* SC, bool check_done = true) {
   const int M = (int)c->M, N = (int)c->N;
   const DevState* st = check_done ? c->st : nullptr;
-  TRY(split(c, HC, c->HC_p, (int64_t)M * N, check_done));
-  TRY(split(c, SC, c->SC_p, (int64_t)M * N, check_done));
-  HIPCHK(c, split_bf16_t(HC, c->HCt_p.hi, c->HCt_p.lo, M, N, st, c->stream));
-  HIPCHK(c, split_bf16_t(SC, c->SCt_p.hi, c->SCt_p.lo, M, N, st, c->stream));
+  TRY(split(c, HC, c->HC_p, M, N, check_done));
+  TRY(split(c, SC, c->SC_p, M, N, check_done));
+  HIPCHK(c, split_bf16_t(HC, c->HCt_p.hi, c->HCt_p.lo, M, N, c->HCt_p.ld, st, c->stream));
+  HIPCHK(c, split_bf16_t(SC, c->SCt_p.hi, c->SCt_p.lo, M, N, c->SCt_p.ld, st, c->stream));
   return OMM_OK;
 }
 
@@ -675,12 +693,12 @@ int initial_products(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* 
   const int et = bf ? T_BF16P : elem_type<T>();
   if (bf) {
     TRY(alloc_iter_planes(c));
-    TRY(split(c, w.C, c->C_p, mn, false));
+    TRY(split(c, w.C, c->C_p, M, N, false));
   }
-  const Opnd Cop = bf ? pl(c->C_p) : dn(w.C);
+  const Opnd Cop = bf ? pl(c->C_p) : dn(w.C, N);
   GemmDesc d{compute, et, et, elem_type<T>(), elem_type<T>(), KC, KC, 0, 1};
-  GemmOp ops[2] = {make_op2(M, N, N, Cop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HC, N),
-                   make_op2(M, N, N, Cop, N, bf ? pl(c->S_p) : dn(S), N, w.SC, N)};
+  GemmOp ops[2] = {make_op2(M, N, N, Cop, bf ? pl(c->Hs_p) : dn(Hs, N), w.HC, N),
+                   make_op2(M, N, N, Cop, bf ? pl(c->S_p) : dn(S, N), w.SC, N)};
   // reduced problem (S~ = I): SC = C, kept as its own copy, which every update then moves
   // exactly like C
   const bool sid = reduced(c);
@@ -689,8 +707,8 @@ int initial_products(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* 
     HIPCHK(c, hipMemcpyAsync(w.SC, w.C, mn * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
   if (bf) TRY(split_state(c, w.HC, w.SC, false));
   GemmDesc d2{compute, et, et, T_F64, T_F64, KC, KC, 0, 1};
-  GemmOp ops2[2] = {make_op2(M, M, N, bf ? pl(c->HC_p) : dn(w.HC), N, Cop, N, c->HW, M),
-                    make_op2(M, M, N, bf ? pl(c->SC_p) : dn(w.SC), N, Cop, N, c->SW, M)};
+  GemmOp ops2[2] = {make_op2(M, M, N, bf ? pl(c->HC_p) : dn(w.HC, N), Cop, c->HW, M),
+                    make_op2(M, M, N, bf ? pl(c->SC_p) : dn(w.SC, N), Cop, c->SW, M)};
   TRY(gemm(c, d2, ops2, 2, nullptr));
   HIPCHK(c, energy_init(c->HW, c->SW, M, c->partials, c->st, trace, c->stream));
   return OMM_OK;
@@ -750,22 +768,20 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   // G = 8 HC - 4 HW SC - 4 SW HC
   {
     if (bf) {
-      TRY(split(c, c->HW, c->HW_p, (int64_t)M * M));
-      TRY(split(c, c->SW, c->SW_p, (int64_t)M * M));
+      TRY(split(c, c->HW, c->HW_p, M, M));
+      TRY(split(c, c->SW, c->SW_p, M, M));
     }
     // BF16x3 reads the transposed planes of SC, HC (k-contiguous); the others read SC, HC by rows
     GemmDesc d{compute, bf ? T_BF16P : T_F64, ot, et, et, KC, bf ? KC : RC, 0, 1};
-    GemmOp op = make_op2(M, N, M, bf ? pl(c->HW_p) : dn(c->HW), M, bf ? pl(c->SCt_p) : dn(w.SC),
-                         bf ? M : N, G, N, -4.0, w.HC, N, 8.0);
-    const Opnd a2 = bf ? pl(c->SW_p) : dn(c->SW), b2 = bf ? pl(c->HCt_p) : dn(w.HC);
+    GemmOp op = make_op2(M, N, M, bf ? pl(c->HW_p) : dn(c->HW, M), bf ? pl(c->SCt_p) : dn(w.SC, N),
+                         G, N, -4.0, w.HC, N, 8.0);
+    const Opnd a2 = bf ? pl(c->SW_p) : dn(c->SW, M), b2 = bf ? pl(c->HCt_p) : dn(w.HC, N);
     op.nseg = 2;
-    op.A[1] = a2.p; op.Alo[1] = a2.lo; op.lda[1] = M;
-    op.B[1] = b2.p; op.Blo[1] = b2.lo; op.ldb[1] = bf ? M : N;
+    op.A[1] = a2.p; op.Alo[1] = a2.lo; op.lda[1] = a2.ld;
+    op.B[1] = b2.p; op.Blo[1] = b2.lo; op.ldb[1] = b2.ld;
     op.K[1] = M;
-    if (fuse && c->p_kind > 0) {  // G's planes for the preconditioner product, from the epilogue
-      op.Chi = c->G_p.hi;
-      op.Clo = c->G_p.lo;
-    }
+    // G's planes for the preconditioner product, from the epilogue
+    if (fuse && c->p_kind > 0) out_planes(op, c->G_p);
     TRY(gemm(c, d, &op, 1, done));
   }
   TRY(prof_mark(c));
@@ -776,24 +792,24 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   const int cP = bf ? CBF16X2B : compute, cD = bf ? CBF16X2A : compute;
   T* PG = G;
   if (c->p_kind > 0) {
-    if (bf && !fuse) TRY(split(c, G, c->G_p, mn));
+    if (bf && !fuse) TRY(split(c, G, c->G_p, M, N));
     GemmDesc d{cP, ot, ot, et, et, KC, KC, 0, 1};
-    GemmOp op = make_op2(M, N, N, bf ? pl(c->G_p) : dn(G), N, bf ? pl(c->P_p) : dn(P), N, w.PG, N);
+    GemmOp op = make_op2(M, N, N, bf ? pl(c->G_p) : dn(G, N), bf ? pl(c->P_p) : dn(P, N), w.PG, N);
     TRY(gemm(c, d, &op, 1, done));
     PG = w.PG;
   }
   TRY(prof_mark(c));
   HIPCHK(c, beta_and_direction<T>(G, PG, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials, c->st,
-                                  c->stream, bf ? c->D_p.hi : nullptr));
+                                  c->stream, bf ? c->D_p.hi : nullptr, N, c->D_p.ld));
   TRY(prof_mark(c));
-  const Opnd Dop = bf ? pl(c->D_p) : dn(w.D);
+  const Opnd Dop = bf ? pl(c->D_p) : dn(w.D, N);
   // reduced problem (S~ = I): SD = D, no product
   const bool sid = reduced(c);
   T* SD = sid ? w.D : w.SD;
   {
     GemmDesc d{cD, ot, ot, et, et, KC, KC, 0, 1};
-    GemmOp ops[2] = {make_op2(M, N, N, Dop, N, bf ? pl(c->Hs_p) : dn(Hs), N, w.HD, N),
-                     make_op2(M, N, N, Dop, N, bf ? pl(c->S_p) : dn(S), N, w.SD, N)};
+    GemmOp ops[2] = {make_op2(M, N, N, Dop, bf ? pl(c->Hs_p) : dn(Hs, N), w.HD, N),
+                     make_op2(M, N, N, Dop, bf ? pl(c->S_p) : dn(S, N), w.SD, N)};
     if (bf && sparse_products(c)) {
       for (int i = 0; i < 2; ++i) {
         ops[i].kptr = c->kl_ptr[i];
@@ -801,25 +817,23 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
       }
     }
     if (fuse) {  // the projection stage's operand planes, from the epilogue
-      ops[0].Chi = c->HD_p.hi;
-      ops[0].Clo = c->HD_p.lo;
-      ops[1].Chi = c->SD_p.hi;
-      ops[1].Clo = c->SD_p.lo;
+      out_planes(ops[0], c->HD_p);
+      out_planes(ops[1], c->SD_p);
     }
     TRY(gemm(c, d, ops, sid ? 1 : 2, done));
   }
   TRY(prof_mark(c));
   if (bf && !fuse) {  // the projection stage's operand planes (D's lo plane stays zero)
-    TRY(split(c, w.HD, c->HD_p, mn));
-    if (!sid) TRY(split(c, w.SD, c->SD_p, mn));
+    TRY(split(c, w.HD, c->HD_p, M, N));
+    if (!sid) TRY(split(c, w.SD, c->SD_p, M, N));
   }
   const Plane& SD_p = sid ? c->D_p : c->SD_p;
   {
     GemmDesc d{cD, ot, ot, T_F64, T_F64, KC, KC, 0, 1};
-    GemmOp ops[4] = {make_op2(M, M, N, Dop, N, bf ? pl(c->HC_p) : dn(w.HC), N, c->H1, M),
-                     make_op2(M, M, N, Dop, N, bf ? pl(c->SC_p) : dn(w.SC), N, c->S1, M),
-                     make_op2(M, M, N, Dop, N, bf ? pl(c->HD_p) : dn(w.HD), N, c->H2, M),
-                     make_op2(M, M, N, Dop, N, bf ? pl(SD_p) : dn(SD), N, c->S2, M)};
+    GemmOp ops[4] = {make_op2(M, M, N, Dop, bf ? pl(c->HC_p) : dn(w.HC, N), c->H1, M),
+                     make_op2(M, M, N, Dop, bf ? pl(c->SC_p) : dn(w.SC, N), c->S1, M),
+                     make_op2(M, M, N, Dop, bf ? pl(c->HD_p) : dn(w.HD, N), c->H2, M),
+                     make_op2(M, M, N, Dop, bf ? pl(SD_p) : dn(SD, N), c->S2, M)};
     TRY(gemm(c, d, ops, 4, done));
   }
   TRY(prof_mark(c));
@@ -828,7 +842,8 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   TRY(prof_mark(c));
   if (fuse) {  // with the planes of the new HC, SC and of their transposes
     const StatePlanes sp{c->HC_p.hi,  c->HC_p.lo,  c->SC_p.hi,  c->SC_p.lo,
-                         c->HCt_p.hi, c->HCt_p.lo, c->SCt_p.hi, c->SCt_p.lo};
+                         c->HCt_p.hi, c->HCt_p.lo, c->SCt_p.hi, c->SCt_p.lo,
+                         c->HC_p.ld,  c->HCt_p.ld};
     HIPCHK(c, update_coefficients_split<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, M, N, sp, c->st,
                                            c->stream));
   } else {

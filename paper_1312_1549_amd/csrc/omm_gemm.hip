@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void splitk_reduce(GemmBatch batch, const int*
     const int row = (int)(idx / op.N), col = (int)(idx % op.N);
     double v = op.alpha * s;
     if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
-    store_out<TC>(op, (int64_t)row * op.ldc + col, v);
+    store_out<TC>(op, row, col, v);
   }
 }
 }  // namespace

@@ -362,14 +362,15 @@ struct AccT<CF64> {
   typedef d4 type;
 };
 
-// Stores output element e = row * ldc + col and, if the op asks for them, its bf16 planes.
+// Stores output element (row, col) and, if the op asks for them, its bf16 planes.
 template <typename TC>
-__device__ __forceinline__ void store_out(const GemmOp& op, int64_t e, double v) {
+__device__ __forceinline__ void store_out(const GemmOp& op, int row, int col, double v) {
   const TC c = (TC)v;
-  static_cast<TC*>(op.C)[e] = c;
+  static_cast<TC*>(op.C)[(int64_t)row * op.ldc + col] = c;
   if (op.Chi) {
     const double w = (double)c;
     const unsigned short h = bf16_rne((float)w);
+    const int64_t e = (int64_t)row * op.ldp + col;
     static_cast<unsigned short*>(op.Chi)[e] = h;
     static_cast<unsigned short*>(op.Clo)[e] = bf16_rne((float)(w - (double)bf16_val(h)));
   }
@@ -397,7 +398,7 @@ __device__ __forceinline__ void store_acc(const GemmOp& op, const acc_t (&acc)[T
           } else {
             double v = op.alpha * s;
             if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
-            store_out<TC>(op, (int64_t)row * op.ldc + col, v);
+            store_out<TC>(op, row, col, v);
           }
         }
       }
@@ -895,7 +896,7 @@ __global__ __launch_bounds__(256) void gemm_sk_fixup(GemmBatch batch, const int*
     if (row < op.M && col < op.N) {
       double v = op.alpha * sum;
       if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
-      store_out<TC>(op, (int64_t)row * op.ldc + col, v);
+      store_out<TC>(op, row, col, v);
     }
   }
 }

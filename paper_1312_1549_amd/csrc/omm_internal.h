@@ -59,10 +59,11 @@ struct GemmOp {
   // zeros, so the result equals the dense product (up to the sign of zero).
   const int* kptr;
   const int* kidx;
-  // Optional bf16 planes of the output (nullable; same layout and leading dimension as C):
-  // Chi = bf16(c), Clo = bf16(c - Chi) of each stored element c, for the next product's operand.
+  // Optional bf16 planes of the output (nullable; row length ldp): Chi = bf16(c),
+  // Clo = bf16(c - Chi) of each stored element c, for the next product's operand.
   void* Chi;
   void* Clo;
+  int64_t ldp;
 };
 
 struct GemmDesc {
@@ -110,16 +111,18 @@ constexpr int NCOEF = 13;
 hipError_t shift_hamiltonian(const double* H, const double* S, double eta, double* Hs, int64_t n,
                              hipStream_t s);
 hipError_t convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
-// hi = bf16(x), lo = bf16(x - hi) (round to nearest even), skipped when st->done.
-hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, int64_t n,
-                      const DevState* st, hipStream_t s);
-hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t n,
-                      const DevState* st, hipStream_t s);
-// Planes of the transpose: src is rows x cols row-major, hi/lo are cols x rows row-major.
+// hi = bf16(x), lo = bf16(x - hi) (round to nearest even), skipped when st->done. src is rows x
+// cols (contiguous); hi/lo rows have length ld (>= cols, a multiple of 4; rows <= 65535).
+hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, int64_t rows,
+                      int64_t cols, int64_t ld, const DevState* st, hipStream_t s);
+hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t rows,
+                      int64_t cols, int64_t ld, const DevState* st, hipStream_t s);
+// Planes of the transpose: src is rows x cols row-major, hi/lo are cols x rows with row length
+// ld >= rows.
 hipError_t split_bf16_t(const float* src, unsigned short* hi, unsigned short* lo, int rows,
-                        int cols, const DevState* st, hipStream_t s);
+                        int cols, int64_t ld, const DevState* st, hipStream_t s);
 hipError_t split_bf16_t(const double* src, unsigned short* hi, unsigned short* lo, int rows,
-                        int cols, const DevState* st, hipStream_t s);
+                        int cols, int64_t ld, const DevState* st, hipStream_t s);
 hipError_t convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 hipError_t copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
 hipError_t validate_symmetric(const double* A, int64_t n, double rtol, int* flags, hipStream_t s);
@@ -130,11 +133,12 @@ hipError_t energy_init(const double* HW, const double* SW, int M, double* partia
                        double* trace, hipStream_t s);
 
 // Polak-Ribiere beta and D = -PG + beta D. With `hi` non-null D is rounded to bf16 in place and
-// its bits are written to `hi` (the single-plane operand of the two-product GEMMs).
+// its bits are written to `hi` (the single-plane operand of the two-product GEMMs): D is then
+// (n / cols) x cols and hi has rows of length ld.
 template <typename T>
 hipError_t beta_and_direction(const T* G, const T* PG, const T* Gprev, T* D, int64_t n, int first,
                               double* partials, DevState* st, hipStream_t s,
-                              unsigned short* hi = nullptr);
+                              unsigned short* hi = nullptr, int64_t cols = 0, int64_t ld = 0);
 
 hipError_t line_search(const double* HW, const double* SW, const double* H1, const double* S1,
                        const double* H2, const double* S2, int M, double* partials, DevState* st,
@@ -144,10 +148,12 @@ template <typename T>
 hipError_t update_coefficients(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
                                const DevState* st, hipStream_t s);
 
-// bf16 hi/lo planes of HC and SC (rows x cols) and of their transposes (cols x rows).
+// bf16 hi/lo planes of HC and SC (rows x cols, row length ld) and of their transposes (cols x
+// rows, row length ldt).
 struct StatePlanes {
   unsigned short *hc_hi, *hc_lo, *sc_hi, *sc_lo;
   unsigned short *hct_hi, *hct_lo, *sct_hi, *sct_lo;
+  int64_t ld, ldt;
 };
 // update_coefficients (rows x cols arrays) fused with the splits of the new HC and SC into `p`
 // (the same values split_bf16 and split_bf16_t would write).

@@ -58,38 +58,44 @@ __device__ __forceinline__ unsigned short bf16_bits(float f) {
   return (unsigned short)(u >> 16);
 }
 
-// hi/lo bf16 planes of src; 4 elements per thread step (8-byte stores).
+// hi/lo bf16 planes of src (rows x cols, contiguous) into rows of length ld >= cols (ld a
+// multiple of 4): one row per blockIdx.y, 4 elements per thread (8-byte stores).
 template <typename T>
-__global__ void k_split(const T* src, unsigned short* hi, unsigned short* lo, int64_t n,
-                        const DevState* st) {
+__global__ void k_split(const T* src, unsigned short* hi, unsigned short* lo, int64_t cols,
+                        int64_t ld, const DevState* st) {
   if (st && st->done) return;
-  const int64_t n4 = n / 4;
   typedef unsigned short us4 __attribute__((ext_vector_type(4)));
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n4; i += (int64_t)gridDim.x * NT) {
-    us4 h, l;
+  const int64_t r = blockIdx.y;
+  const T* srow = src + r * cols;
+  for (int64_t c4 = ((int64_t)blockIdx.x * NT + threadIdx.x) * 4; c4 < cols;
+       c4 += (int64_t)gridDim.x * NT * 4) {
+    if (c4 + 4 <= cols) {
+      us4 h, l;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double v = (double)src[4 * i + u];
-      const unsigned short hb = bf16_bits((float)v);
-      h[u] = hb;
-      l[u] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+      for (int u = 0; u < 4; ++u) {
+        const double v = (double)srow[c4 + u];
+        const unsigned short hb = bf16_bits((float)v);
+        h[u] = hb;
+        l[u] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+      }
+      *reinterpret_cast<us4*>(hi + r * ld + c4) = h;
+      *reinterpret_cast<us4*>(lo + r * ld + c4) = l;
+    } else {
+      for (int64_t c = c4; c < cols; ++c) {
+        const double v = (double)srow[c];
+        const unsigned short hb = bf16_bits((float)v);
+        hi[r * ld + c] = hb;
+        lo[r * ld + c] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+      }
     }
-    *reinterpret_cast<us4*>(hi + 4 * i) = h;
-    *reinterpret_cast<us4*>(lo + 4 * i) = l;
-  }
-  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
-    const int64_t i = 4 * n4 + threadIdx.x;
-    const double v = (double)src[i];
-    const unsigned short hb = bf16_bits((float)v);
-    hi[i] = hb;
-    lo[i] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
   }
 }
 
-// Transposing split through a 32 x 33 LDS tile: dst (cols x rows) = planes of src^T.
+// Transposing split through a 32 x 33 LDS tile: dst (cols x rows, row length ld) = planes of
+// src^T.
 template <typename T>
 __global__ void k_split_t(const T* src, unsigned short* hi, unsigned short* lo, int rows, int cols,
-                          const DevState* st) {
+                          int64_t ld, const DevState* st) {
   if (st && st->done) return;
   __shared__ T t[32][33];
   const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
@@ -104,7 +110,7 @@ __global__ void k_split_t(const T* src, unsigned short* hi, unsigned short* lo, 
     if (oc < cols && orow < rows) {
       const double v = (double)t[tx][r];
       const unsigned short hb = bf16_bits((float)v);
-      const int64_t o = (int64_t)oc * rows + orow;
+      const int64_t o = (int64_t)oc * ld + orow;
       hi[o] = hb;
       lo[o] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
     }
@@ -287,15 +293,19 @@ __global__ void k_direction(const T* PG, T* D, int64_t n, int first, const DevSt
 
 // The same direction rounded to bf16: D keeps the rounded values (exact in T) and `hi` their bf16
 // bits, so the products with D need no lo plane and the CG update moves along exactly this D.
+// D = -PG + beta D (rows x cols) rounded to bf16: the bits go to hi (row length ld) and the
+// rounded value back to D. One row per blockIdx.y.
 template <typename T>
-__global__ void k_direction_bf16(const T* PG, T* D, unsigned short* hi, int64_t n, int first,
-                                 const DevState* st) {
+__global__ void k_direction_bf16(const T* PG, T* D, unsigned short* hi, int64_t cols, int64_t ld,
+                                 int first, const DevState* st) {
   if (st->done) return;
   const double beta = st->beta;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+  const int64_t r = blockIdx.y;
+  for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < cols; c += (int64_t)gridDim.x * NT) {
+    const int64_t i = r * cols + c;
     const double d = first ? -(double)PG[i] : -(double)PG[i] + beta * (double)D[i];
     const unsigned short hb = bf16_bits((float)d);
-    hi[i] = hb;
+    hi[r * ld + c] = hb;
     D[i] = (T)__uint_as_float(((unsigned int)hb) << 16);
   }
 }
@@ -506,8 +516,9 @@ __global__ void k_update_split_mn(T* C, const T* D, T* HC, const T* HD, T* SC, c
       v = (T)((double)SC[e] + x * (double)SD[e]);
       HC[e] = h;
       SC[e] = v;
-      split_store((double)h, p.hc_hi, p.hc_lo, e);
-      split_store((double)v, p.sc_hi, p.sc_lo, e);
+      const int64_t q = (int64_t)gr * p.ld + gc;
+      split_store((double)h, p.hc_hi, p.hc_lo, q);
+      split_store((double)v, p.sc_hi, p.sc_lo, q);
     }
     th[r][tx] = h;
     ts[r][tx] = v;
@@ -516,7 +527,7 @@ __global__ void k_update_split_mn(T* C, const T* D, T* HC, const T* HD, T* SC, c
   for (int r = ty; r < 32; r += 8) {
     const int oc = c0 + r, orow = r0 + tx;  // output row oc (a source column), column orow
     if (oc < cols && orow < rows) {
-      const int64_t o = (int64_t)oc * rows + orow;
+      const int64_t o = (int64_t)oc * p.ldt + orow;
       split_store((double)th[tx][r], p.hct_hi, p.hct_lo, o);
       split_store((double)ts[tx][r], p.sct_hi, p.sct_lo, o);
     }
@@ -687,29 +698,47 @@ hipError_t convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, int64_t n,
-                      const DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_split<float>, dim3(ew_blocks(n / 4 + 1)), dim3(NT), 0, s, src, hi, lo, n, st);
+namespace {
+dim3 split_grid(int64_t rows, int64_t cols) {
+  int64_t bx = (cols + 4 * NT - 1) / (4 * NT);
+  if (bx < 1) bx = 1;
+  return dim3((unsigned)bx, (unsigned)rows);
+}
+}  // namespace
+
+hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, int64_t rows,
+                      int64_t cols, int64_t ld, const DevState* st, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (rows > 65535 || ld < cols || ld % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split<float>, split_grid(rows, cols), dim3(NT), 0, s, src, hi, lo, cols, ld,
+                     st);
   return hipGetLastError();
 }
 
-hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t n,
-                      const DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_split<double>, dim3(ew_blocks(n / 4 + 1)), dim3(NT), 0, s, src, hi, lo, n, st);
+hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t rows,
+                      int64_t cols, int64_t ld, const DevState* st, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (rows > 65535 || ld < cols || ld % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split<double>, split_grid(rows, cols), dim3(NT), 0, s, src, hi, lo, cols, ld,
+                     st);
   return hipGetLastError();
 }
 
 hipError_t split_bf16_t(const float* src, unsigned short* hi, unsigned short* lo, int rows,
-                        int cols, const DevState* st, hipStream_t s) {
+                        int cols, int64_t ld, const DevState* st, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (ld < rows) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_split_t<float>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0, s, src,
-                     hi, lo, rows, cols, st);
+                     hi, lo, rows, cols, ld, st);
   return hipGetLastError();
 }
 
 hipError_t split_bf16_t(const double* src, unsigned short* hi, unsigned short* lo, int rows,
-                        int cols, const DevState* st, hipStream_t s) {
+                        int cols, int64_t ld, const DevState* st, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (ld < rows) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_split_t<double>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0, s,
-                     src, hi, lo, rows, cols, st);
+                     src, hi, lo, rows, cols, ld, st);
   return hipGetLastError();
 }
 
@@ -752,24 +781,28 @@ hipError_t block_pattern(const double* B, int64_t n, unsigned char* flags, hipSt
 
 template <typename T>
 hipError_t beta_and_direction(const T* G, const T* PG, const T* Gprev, T* D, int64_t n, int first,
-                              double* partials, DevState* st, hipStream_t s, unsigned short* hi) {
+                              double* partials, DevState* st, hipStream_t s, unsigned short* hi,
+                              int64_t cols, int64_t ld) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_pr_partials<T>, dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first, partials,
                      st);
   hipLaunchKernelGGL(k_pr_final, dim3(1), dim3(NT), 0, s, partials, nb, first, st);
-  if (hi)
-    hipLaunchKernelGGL(k_direction_bf16<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, hi, n, first,
-                       st);
-  else
+  if (hi) {
+    if (cols <= 0 || n % cols != 0 || n / cols > 65535 || ld < cols) return hipErrorInvalidValue;
+    int64_t bx = (cols + NT - 1) / NT;
+    hipLaunchKernelGGL(k_direction_bf16<T>, dim3((unsigned)bx, (unsigned)(n / cols)), dim3(NT), 0, s,
+                       PG, D, hi, cols, ld, first, st);
+  } else {
     hipLaunchKernelGGL(k_direction<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, n, first, st);
+  }
   return hipGetLastError();
 }
 template hipError_t beta_and_direction<double>(const double*, const double*, const double*,
                                                double*, int64_t, int, double*, DevState*,
-                                               hipStream_t, unsigned short*);
+                                               hipStream_t, unsigned short*, int64_t, int64_t);
 template hipError_t beta_and_direction<float>(const float*, const float*, const float*, float*,
                                               int64_t, int, double*, DevState*, hipStream_t,
-                                              unsigned short*);
+                                              unsigned short*, int64_t, int64_t);
 
 hipError_t line_search(const double* HW, const double* SW, const double* H1, const double* S1,
                        const double* H2, const double* S2, int M, double* partials, DevState* st,
@@ -800,6 +833,7 @@ hipError_t update_coefficients_split(T* C, const T* D, T* HC, const T* HD, T* SC
                                      int rows, int cols, const StatePlanes& p, const DevState* st,
                                      hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (p.ld < cols || p.ldt < rows) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_update_split_mn<T>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0, s,
                      C, D, HC, HD, SC, SD, rows, cols, p, st);
   return hipGetLastError();
