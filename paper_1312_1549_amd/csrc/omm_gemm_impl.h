@@ -622,15 +622,17 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
         ldp[p] = op.ldb[seg]; row0[p] = n0; rmax[p] = op.N; ++p;
       }
     }
-    // per-lane source of each of this wave's DPS wave loads (k offset added per stage)
-    const unsigned short* src[DPS];
+    // per-lane byte offset (32 bits: the plane base stays a wave-uniform scalar) of each of
+    // this wave's DPS wave loads; the k offset is added per stage. Wave chunk q = wave + 8 i
+    // covers plane q / 16 = i / 2 (8 waves), rows 16 (q % 16) ..
+    static_assert(NT == 512, "eight waves: wave chunk i lies in plane i / 2");
+    unsigned off[DPS];
     int dst[DPS];  // LDS element offset within a stage buffer (wave-uniform)
 #pragma unroll
     for (int i = 0; i < DPS; ++i) {
-      const int q = wave + 8 * i;  // wave chunk: plane q / 16, rows 16 (q % 16) ..
-      const int pl = q / 16, j = q % 16;
+      const int pl = i >> 1, j = wave + 8 * (i & 1);
       const int gr = min(row0[pl] + 16 * j + lrow, rmax[pl] - 1);
-      src[i] = plane[pl] + (int64_t)gr * ldp[pl] + 8 * lchunk;
+      off[i] = (unsigned)(2 * ((int64_t)gr * ldp[pl] + 8 * lchunk));  // bytes
       dst[i] = pl * DMA_PLANE + 512 * j;
     }
     // dense: stages kb, kb + BK, ...; block-sparse B: the listed K blocks of this column tile
@@ -645,7 +647,9 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
       if (full(st)) {
 #pragma unroll
         for (int i = 0; i < DPS; ++i)
-          __builtin_amdgcn_global_load_lds(src[i] + k0, buf + dst[i], 16, 0, 0);
+          __builtin_amdgcn_global_load_lds(
+              reinterpret_cast<const char*>(plane[i >> 1]) + (off[i] + 2u * (unsigned)k0),
+              buf + dst[i], 16, 0, 0);
       } else {
         SA sa;
         SB sb;
@@ -806,26 +810,29 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_sk(GemmBatch batch, const 
     tm = t % tiles_m;
     tn = t / tiles_m;
   };
-  // data-parallel rounds: whole tiles
-  for (int r = 0; r < a.R; ++r) {
-    const GemmOp* op;
-    int tm, tn;
-    locate(r * G + h, op, tm, tn);
-    gemm_tile_dma_acc<MODE, NS, DmaUser<1, TC>>(*op, tm, tn, 0, ktot, acc);
-    store_acc<MODE, TC, TX, DMA_TM, DMA_TN>(*op, acc, tm * DMA_BM + (wave % 2) * DMA_TM * 16,
-                                            tn * DMA_BN + (wave / 2) * DMA_TN * 16, lane, 0, 1,
-                                            nullptr, 0, 1);
-  }
-  // cut tiles: this workgroup's share of the remaining K steps
+  // One loop over this workgroup's work items (one call site of the tile loop and of the
+  // epilogue): first the data-parallel rounds (whole tiles), then its share [u0, u1) of the K
+  // steps of the cut tiles.
   const int64_t u0 = sk_bound(a.W, h, G), u1 = sk_bound(a.W, h + 1, G);
-  int part = 0;
-  for (int64_t u = u0; u < u1; ++part) {
-    const int q = (int)(u / a.nk);  // cut tile index
-    const int k0 = (int)(u - (int64_t)q * a.nk);
-    const int k1 = (int)min((int64_t)a.nk, k0 + (u1 - u));
+  int r = 0, part = 0;
+  int64_t u = u0;
+  while (r < a.R || u < u1) {
+    int to, k0, k1;
+    if (r < a.R) {
+      to = r * G + h;
+      k0 = 0;
+      k1 = a.nk;
+      ++r;
+    } else {
+      const int q = (int)(u / a.nk);  // cut tile index
+      to = a.R * G + q;
+      k0 = (int)(u - (int64_t)q * a.nk);
+      k1 = (int)min((int64_t)a.nk, k0 + (u1 - u));
+      u += k1 - k0;
+    }
     const GemmOp* op;
     int tm, tn;
-    locate(a.R * G + q, op, tm, tn);
+    locate(to, op, tm, tn);
     gemm_tile_dma_acc<MODE, NS, DmaUser<1, TC>>(*op, tm, tn, k0 * DMA_BK, min(ktot, k1 * DMA_BK),
                                                 acc);
     if (k0 == 0 && k1 == a.nk) {
@@ -839,10 +846,10 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_sk(GemmBatch batch, const 
 #pragma unroll
         for (int j = 0; j < DMA_TN; ++j)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            slot[((i * DMA_TN + j) * 4 + r) * 512 + threadIdx.x] = acc[i][j][r];
+          for (int e = 0; e < 4; ++e)
+            slot[((i * DMA_TN + j) * 4 + e) * 512 + threadIdx.x] = acc[i][j][e];
+      ++part;
     }
-    u += k1 - k0;
   }
 }
 
