@@ -534,6 +534,102 @@ __global__ void k_update_split_mn(T* C, const T* D, T* HC, const T* HD, T* SC, c
   }
 }
 
+// The same for an even number of columns (8-byte aligned rows), one 64 x 64 tile per block:
+// each thread takes two adjacent columns, so the T arrays move in 16-byte and the planes in
+// 4-byte (two bf16) accesses, and every plane row segment a block writes (also transposed) is
+// one 128-byte line. The transpose goes through LDS as packed (hi | lo << 16) words.
+__device__ __forceinline__ unsigned split_word(double v) {
+  const unsigned hb = bf16_bits((float)v);
+  const unsigned lb = bf16_bits((float)(v - (double)__uint_as_float(hb << 16)));
+  return hb | (lb << 16);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC, const T* HD,
+                                                         T* SC, const T* SD, int rows, int cols,
+                                                         StatePlanes p, const DevState* st) {
+  if (st->done) return;
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  __shared__ unsigned th[64][65], ts[64][65];
+  const double x = st->x;
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 column pairs x 8 rows
+  const int gc = c0 + 2 * tx;
+  // rows ty + 8 k, four at a time: all loads of a batch are issued before its stores
+  constexpr int RB = 4;
+#pragma unroll
+  for (int b = 0; b < 8; b += RB) {
+    T2 c[RB], d[RB], hc[RB], hd[RB], sc[RB], sd[RB];
+    bool in[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int gr = r0 + ty + 8 * (b + k);
+      in[k] = gr < rows && gc < cols;  // cols even: gc + 1 < cols as well
+      if (in[k]) {
+        const int64_t e = (int64_t)gr * cols + gc;
+        c[k] = *reinterpret_cast<const T2*>(C + e);
+        d[k] = *reinterpret_cast<const T2*>(D + e);
+        hc[k] = *reinterpret_cast<const T2*>(HC + e);
+        hd[k] = *reinterpret_cast<const T2*>(HD + e);
+        sc[k] = *reinterpret_cast<const T2*>(SC + e);
+        sd[k] = *reinterpret_cast<const T2*>(SD + e);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int r = ty + 8 * (b + k), gr = r0 + r;
+      unsigned wh0 = 0, wh1 = 0, ws0 = 0, ws1 = 0;
+      if (in[k]) {
+        const int64_t e = (int64_t)gr * cols + gc;
+        T2 cn, h, v;
+        cn.x = (T)((double)c[k].x + x * (double)d[k].x);
+        cn.y = (T)((double)c[k].y + x * (double)d[k].y);
+        h.x = (T)((double)hc[k].x + x * (double)hd[k].x);
+        h.y = (T)((double)hc[k].y + x * (double)hd[k].y);
+        v.x = (T)((double)sc[k].x + x * (double)sd[k].x);
+        v.y = (T)((double)sc[k].y + x * (double)sd[k].y);
+        *reinterpret_cast<T2*>(C + e) = cn;
+        *reinterpret_cast<T2*>(HC + e) = h;
+        *reinterpret_cast<T2*>(SC + e) = v;
+        wh0 = split_word((double)h.x);
+        wh1 = split_word((double)h.y);
+        ws0 = split_word((double)v.x);
+        ws1 = split_word((double)v.y);
+        const int64_t q = (int64_t)gr * p.ld + gc;
+        *reinterpret_cast<unsigned*>(p.hc_hi + q) = (wh0 & 0xffffu) | (wh1 << 16);
+        *reinterpret_cast<unsigned*>(p.hc_lo + q) = (wh0 >> 16) | (wh1 & 0xffff0000u);
+        *reinterpret_cast<unsigned*>(p.sc_hi + q) = (ws0 & 0xffffu) | (ws1 << 16);
+        *reinterpret_cast<unsigned*>(p.sc_lo + q) = (ws0 >> 16) | (ws1 & 0xffff0000u);
+      }
+      th[r][2 * tx] = wh0;
+      th[r][2 * tx + 1] = wh1;
+      ts[r][2 * tx] = ws0;
+      ts[r][2 * tx + 1] = ws1;
+    }
+  }
+  __syncthreads();
+  // transposed: output row oc = c0 + j (a source column), output columns r0 + 2 tx, r0 + 2 tx + 1
+  const int orow = r0 + 2 * tx;
+  for (int j = ty; j < 64; j += 8) {
+    const int oc = c0 + j;
+    if (oc >= cols || orow >= rows) continue;
+    const unsigned a0 = th[2 * tx][j], b0 = ts[2 * tx][j];
+    const int64_t o = (int64_t)oc * p.ldt + orow;
+    if (orow + 1 < rows) {
+      const unsigned a1 = th[2 * tx + 1][j], b1 = ts[2 * tx + 1][j];
+      *reinterpret_cast<unsigned*>(p.hct_hi + o) = (a0 & 0xffffu) | (a1 << 16);
+      *reinterpret_cast<unsigned*>(p.hct_lo + o) = (a0 >> 16) | (a1 & 0xffff0000u);
+      *reinterpret_cast<unsigned*>(p.sct_hi + o) = (b0 & 0xffffu) | (b1 << 16);
+      *reinterpret_cast<unsigned*>(p.sct_lo + o) = (b0 >> 16) | (b1 & 0xffff0000u);
+    } else {
+      p.hct_hi[o] = (unsigned short)(a0 & 0xffffu);
+      p.hct_lo[o] = (unsigned short)(a0 >> 16);
+      p.sct_hi[o] = (unsigned short)(b0 & 0xffffu);
+      p.sct_lo[o] = (unsigned short)(b0 >> 16);
+    }
+  }
+}
+
 // HW += x (H' + H'^T) + x^2 H'', SW likewise; partial sums of Tr HW, <SW, HW>, Tr SW.
 __device__ __forceinline__ void b_update_mm(double* HW, double* SW, const double* H1, const double* S1,
                             const double* H2, const double* S2, int M, double* partials,
@@ -834,8 +930,15 @@ hipError_t update_coefficients_split(T* C, const T* D, T* HC, const T* HD, T* SC
                                      hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   if (p.ld < cols || p.ldt < rows) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_update_split_mn<T>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0, s,
-                     C, D, HC, HD, SC, SD, rows, cols, p, st);
+  const bool wide = cols % 2 == 0 && p.ld % 2 == 0 && p.ldt % 2 == 0 &&
+                    ((uintptr_t)C | (uintptr_t)D | (uintptr_t)HC | (uintptr_t)HD | (uintptr_t)SC |
+                     (uintptr_t)SD) % (2 * sizeof(T)) == 0;
+  if (wide)
+    hipLaunchKernelGGL(k_update_split_mn2<T>, dim3((cols + 63) / 64, (rows + 63) / 64), dim3(NT), 0,
+                       s, C, D, HC, HD, SC, SD, rows, cols, p, st);
+  else
+    hipLaunchKernelGGL(k_update_split_mn<T>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0,
+                       s, C, D, HC, HD, SC, SD, rows, cols, p, st);
   return hipGetLastError();
 }
 template hipError_t update_coefficients_split<double>(double*, const double*, double*,
