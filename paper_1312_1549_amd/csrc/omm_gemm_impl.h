@@ -857,7 +857,7 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_sk(GemmBatch batch, const 
 // takes one of SK_FIX_CHUNKS slices of the tile's elements. Parts and the element each slot
 // entry belongs to follow the layout gemm_kernel_sk writes (entry (i TN + j) 4 + r of thread t
 // at offset ((i TN + j) 4 + r) 512 + t).
-constexpr int SK_FIX_CHUNKS = 8;
+constexpr int SK_FIX_CHUNKS = 32;
 
 template <typename TC, typename TX>
 __global__ __launch_bounds__(256) void gemm_sk_fixup(GemmBatch batch, const int* done, SkArgs a,
@@ -893,8 +893,17 @@ __global__ __launch_bounds__(256) void gemm_sk_fixup(GemmBatch batch, const int*
   const int tm = t % tiles_m, tn = t / tiles_m;
   constexpr int PER = DMA_BM * DMA_BN / SK_FIX_CHUNKS;
   for (int f = blockIdx.y * PER + threadIdx.x; f < (blockIdx.y + 1) * PER; f += 256) {
+    // the parts are added in K order; four loads are in flight at a time
     double sum = 0.0;
-    for (int k = 0; k < n; ++k) sum += (double)parts[(int64_t)slot[k] * (DMA_BM * DMA_BN) + f];
+    int k = 0;
+    for (; k + 4 <= n; k += 4) {
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = parts[(int64_t)slot[k + u] * (DMA_BM * DMA_BN) + f];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sum += (double)v[u];
+    }
+    for (; k < n; ++k) sum += (double)parts[(int64_t)slot[k] * (DMA_BM * DMA_BN) + f];
     const int e = f >> 9, tid = f & 511;  // slot entry and the kernel thread that wrote it
     const int wave = tid >> 6, lane = tid & 63;
     const int i = e / (DMA_TN * 4), j = (e / 4) % DMA_TN, r = e % 4;
