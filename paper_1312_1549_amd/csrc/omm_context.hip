@@ -34,6 +34,10 @@ template <typename T>
 struct Work {
   T *C = nullptr, *HC = nullptr, *SC = nullptr, *G = nullptr, *Gp = nullptr, *PG = nullptr,
     *D = nullptr, *HD = nullptr, *SD = nullptr;
+  // BF16 scheme with an FP64 state: PG, HD and SD held in FP32. Their products accumulate in
+  // FP32, so the FP32 value is the product itself (the stream-K fix-up sums parts in FP64 and
+  // rounds once); the state C, HC, SC, G, D stays FP64.
+  float *PGf = nullptr, *HDf = nullptr, *SDf = nullptr;
 };
 
 // A bf16 hi/lo pair of planes (x = hi + lo) feeding the BF16x3 GEMMs.
@@ -186,6 +190,11 @@ int alloc_work(omm_ctx* c, Work<T>& w) {
   TRY(dalloc(c, &w.D, mn));
   TRY(dalloc(c, &w.HD, mn));
   TRY(dalloc(c, &w.SD, mn));
+  if (sizeof(T) == 8 && c->mode == OMM_BF16X3 && c->refine) {
+    TRY(dalloc(c, &w.PGf, mn));
+    TRY(dalloc(c, &w.HDf, mn));
+    TRY(dalloc(c, &w.SDf, mn));
+  }
   return OMM_OK;
 }
 
@@ -193,6 +202,7 @@ template <typename T>
 void free_work(Work<T>& w) {
   dfree(w.C); dfree(w.HC); dfree(w.SC); dfree(w.G); dfree(w.Gp); dfree(w.PG); dfree(w.D);
   dfree(w.HD); dfree(w.SD);
+  dfree(w.PGf); dfree(w.HDf); dfree(w.SDf);
 }
 
 // Row length of a bf16 plane with `cols` columns: a multiple of 64 elements, so that every row
@@ -791,25 +801,37 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   // operand is exact).
   const int cP = bf ? CBF16X2B : compute, cD = bf ? CBF16X2A : compute;
   T* PG = G;
+  // BF16 with the FP64 state: the products PG, HD, SD are stored in FP32 (see Work)
+  const bool f32p = bf && sizeof(T) == 8 && w.PGf != nullptr;
   if (c->p_kind > 0) {
     if (bf && !fuse) TRY(split(c, G, c->G_p, M, N));
-    GemmDesc d{cP, ot, ot, et, et, KC, KC, 0, 1};
-    GemmOp op = make_op2(M, N, N, bf ? pl(c->G_p) : dn(G, N), bf ? pl(c->P_p) : dn(P, N), w.PG, N);
+    const int tp = f32p ? T_F32 : et;
+    GemmDesc d{cP, ot, ot, tp, tp, KC, KC, 0, 1};
+    GemmOp op = make_op2(M, N, N, bf ? pl(c->G_p) : dn(G, N), bf ? pl(c->P_p) : dn(P, N),
+                         f32p ? (void*)w.PGf : (void*)w.PG, N);
     TRY(gemm(c, d, &op, 1, done));
     PG = w.PG;
   }
   TRY(prof_mark(c));
-  HIPCHK(c, beta_and_direction<T>(G, PG, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials, c->st,
-                                  c->stream, bf ? c->D_p.hi : nullptr, N, c->D_p.ld));
+  if (f32p && c->p_kind > 0)
+    HIPCHK(c, (beta_and_direction<T, float>(G, w.PGf, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials,
+                                           c->st, c->stream, c->D_p.hi, N, c->D_p.ld)));
+  else
+    HIPCHK(c, beta_and_direction<T>(G, PG, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials, c->st,
+                                    c->stream, bf ? c->D_p.hi : nullptr, N, c->D_p.ld));
   TRY(prof_mark(c));
   const Opnd Dop = bf ? pl(c->D_p) : dn(w.D, N);
   // reduced problem (S~ = I): SD = D, no product
   const bool sid = reduced(c);
   T* SD = sid ? w.D : w.SD;
+  const bool hdf = f32p && !sid;  // with S~ = I, SD is D itself (FP64)
   {
-    GemmDesc d{cD, ot, ot, et, et, KC, KC, 0, 1};
-    GemmOp ops[2] = {make_op2(M, N, N, Dop, bf ? pl(c->Hs_p) : dn(Hs, N), w.HD, N),
-                     make_op2(M, N, N, Dop, bf ? pl(c->S_p) : dn(S, N), w.SD, N)};
+    const int td = hdf ? T_F32 : et;
+    GemmDesc d{cD, ot, ot, td, td, KC, KC, 0, 1};
+    GemmOp ops[2] = {make_op2(M, N, N, Dop, bf ? pl(c->Hs_p) : dn(Hs, N),
+                              hdf ? (void*)w.HDf : (void*)w.HD, N),
+                     make_op2(M, N, N, Dop, bf ? pl(c->S_p) : dn(S, N),
+                              hdf ? (void*)w.SDf : (void*)w.SD, N)};
     if (bf && sparse_products(c)) {
       for (int i = 0; i < 2; ++i) {
         ops[i].kptr = c->kl_ptr[i];
@@ -824,8 +846,13 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   }
   TRY(prof_mark(c));
   if (bf && !fuse) {  // the projection stage's operand planes (D's lo plane stays zero)
-    TRY(split(c, w.HD, c->HD_p, M, N));
-    if (!sid) TRY(split(c, w.SD, c->SD_p, M, N));
+    if (hdf) {
+      TRY(split(c, w.HDf, c->HD_p, M, N));
+      TRY(split(c, w.SDf, c->SD_p, M, N));
+    } else {
+      TRY(split(c, w.HD, c->HD_p, M, N));
+      if (!sid) TRY(split(c, w.SD, c->SD_p, M, N));
+    }
   }
   const Plane& SD_p = sid ? c->D_p : c->SD_p;
   {
@@ -844,10 +871,18 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     const StatePlanes sp{c->HC_p.hi,  c->HC_p.lo,  c->SC_p.hi,  c->SC_p.lo,
                          c->HCt_p.hi, c->HCt_p.lo, c->SCt_p.hi, c->SCt_p.lo,
                          c->HC_p.ld,  c->HCt_p.ld};
-    HIPCHK(c, update_coefficients_split<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, M, N, sp, c->st,
-                                           c->stream));
+    if (hdf)
+      HIPCHK(c, (update_coefficients_split<T, float>(w.C, w.D, w.HC, w.HDf, w.SC, w.SDf, M, N, sp,
+                                                    c->st, c->stream)));
+    else
+      HIPCHK(c, update_coefficients_split<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, M, N, sp, c->st,
+                                             c->stream));
   } else {
-    HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, mn, c->st, c->stream));
+    if (hdf)
+      HIPCHK(c, (update_coefficients<T, float>(w.C, w.D, w.HC, w.HDf, w.SC, w.SDf, mn, c->st,
+                                              c->stream)));
+    else
+      HIPCHK(c, update_coefficients<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, mn, c->st, c->stream));
     if (bf) TRY(split_state(c, w.HC, w.SC));
   }
   HIPCHK(c, update_subspace(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,

@@ -135,8 +135,8 @@ hipError_t energy_init(const double* HW, const double* SW, int M, double* partia
 // Polak-Ribiere beta and D = -PG + beta D. With `hi` non-null D is rounded to bf16 in place and
 // its bits are written to `hi` (the single-plane operand of the two-product GEMMs): D is then
 // (n / cols) x cols and hi has rows of length ld.
-template <typename T>
-hipError_t beta_and_direction(const T* G, const T* PG, const T* Gprev, T* D, int64_t n, int first,
+template <typename T, typename TP = T>
+hipError_t beta_and_direction(const T* G, const TP* PG, const T* Gprev, T* D, int64_t n, int first,
                               double* partials, DevState* st, hipStream_t s,
                               unsigned short* hi = nullptr, int64_t cols = 0, int64_t ld = 0);
 
@@ -144,9 +144,11 @@ hipError_t line_search(const double* HW, const double* SW, const double* H1, con
                        const double* H2, const double* S2, int M, double* partials, DevState* st,
                        hipStream_t s);
 
-template <typename T>
-hipError_t update_coefficients(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
-                               const DevState* st, hipStream_t s);
+// HD, SD (type TD) may be held in a narrower type than the state (FP32 products of the BF16
+// scheme with an FP64 state).
+template <typename T, typename TD = T>
+hipError_t update_coefficients(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD,
+                               int64_t n, const DevState* st, hipStream_t s);
 
 // bf16 hi/lo planes of HC and SC (rows x cols, row length ld) and of their transposes (cols x
 // rows, row length ldt).
@@ -157,8 +159,8 @@ struct StatePlanes {
 };
 // update_coefficients (rows x cols arrays) fused with the splits of the new HC and SC into `p`
 // (the same values split_bf16 and split_bf16_t would write).
-template <typename T>
-hipError_t update_coefficients_split(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD,
+template <typename T, typename TD = T>
+hipError_t update_coefficients_split(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD,
                                      int rows, int cols, const StatePlanes& p, const DevState* st,
                                      hipStream_t s);
 

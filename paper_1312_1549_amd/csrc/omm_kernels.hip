@@ -217,8 +217,8 @@ __global__ void k_energy_init_final(const double* partials, int nb, DevState* st
 }
 
 // ---- Polak-Ribiere coefficient and direction ----------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void b_pr_partials(const T* G, const T* PG, const T* Gp, int64_t n, int first,
+template <typename T, typename TP = T>
+__device__ __forceinline__ void b_pr_partials(const T* G, const TP* PG, const T* Gp, int64_t n, int first,
                               double* partials, const DevState* st, int bid, int nb) {
   if (st->done) return;
   __shared__ double sh[NT / 64];
@@ -236,8 +236,8 @@ __device__ __forceinline__ void b_pr_partials(const T* G, const T* PG, const T* 
   }
 }
 
-template <typename T>
-__global__ void k_pr_partials(const T* G, const T* PG, const T* Gp, int64_t n, int first,
+template <typename T, typename TP>
+__global__ void k_pr_partials(const T* G, const TP* PG, const T* Gp, int64_t n, int first,
                               double* partials, const DevState* st) {
   b_pr_partials(G, PG, Gp, n, first, partials, st, blockIdx.x, gridDim.x);
 }
@@ -261,8 +261,8 @@ __global__ void k_pr_final(const double* partials, int nb, int first, DevState* 
   f_pr_final(partials, nb, first, st);
 }
 
-template <typename T>
-__device__ __forceinline__ void b_direction(const T* PG, T* D, int64_t n, int first, const DevState* st, int bid, int nb) {
+template <typename T, typename TP = T>
+__device__ __forceinline__ void b_direction(const TP* PG, T* D, int64_t n, int first, const DevState* st, int bid, int nb) {
   if (st->done) return;
   const double beta = st->beta;
   for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n; i += (int64_t)nb * NT) {
@@ -286,17 +286,16 @@ __global__ void k_block_pattern(const double* B, int64_t n, unsigned char* flags
   if (threadIdx.x == 0) flags[(int64_t)t * nkb + kb] = (unsigned char)nz;
 }
 
-template <typename T>
-__global__ void k_direction(const T* PG, T* D, int64_t n, int first, const DevState* st) {
+template <typename T, typename TP>
+__global__ void k_direction(const TP* PG, T* D, int64_t n, int first, const DevState* st) {
   b_direction(PG, D, n, first, st, blockIdx.x, gridDim.x);
 }
 
 // The same direction rounded to bf16: D keeps the rounded values (exact in T) and `hi` their bf16
-// bits, so the products with D need no lo plane and the CG update moves along exactly this D.
-// D = -PG + beta D (rows x cols) rounded to bf16: the bits go to hi (row length ld) and the
-// rounded value back to D. One row per blockIdx.y.
-template <typename T>
-__global__ void k_direction_bf16(const T* PG, T* D, unsigned short* hi, int64_t cols, int64_t ld,
+// bits (rows of length ld), so the products with D need no lo plane and the CG update moves along
+// exactly this D. One row of D (rows x cols) per blockIdx.y.
+template <typename T, typename TP>
+__global__ void k_direction_bf16(const TP* PG, T* D, unsigned short* hi, int64_t cols, int64_t ld,
                                  int first, const DevState* st) {
   if (st->done) return;
   const double beta = st->beta;
@@ -471,8 +470,8 @@ __global__ void k_line_final(const double* partials, int nb, DevState* st) {
 }
 
 // ---- updates (Eq. 16 and the footnote of Sec. 2.3) ----------------------------------------------
-template <typename T>
-__device__ __forceinline__ void b_update_mn(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
+template <typename T, typename TD = T>
+__device__ __forceinline__ void b_update_mn(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD, int64_t n,
                             const DevState* st, int bid, int nb) {
   if (st->done) return;
   const double x = st->x;
@@ -483,8 +482,8 @@ __device__ __forceinline__ void b_update_mn(T* C, const T* D, T* HC, const T* HD
   }
 }
 
-template <typename T>
-__global__ void k_update_mn(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
+template <typename T, typename TD>
+__global__ void k_update_mn(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD, int64_t n,
                             const DevState* st) {
   b_update_mn(C, D, HC, HD, SC, SD, n, st, blockIdx.x, gridDim.x);
 }
@@ -498,8 +497,8 @@ __device__ __forceinline__ void split_store(double v, unsigned short* hi, unsign
 
 // Eq. 16 for C, HC, SC (rows x cols) with the bf16 planes of the new HC and SC, row-major and
 // transposed (through a 32 x 33 LDS tile), one 32 x 32 tile per block.
-template <typename T>
-__global__ void k_update_split_mn(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD,
+template <typename T, typename TD>
+__global__ void k_update_split_mn(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD,
                                   int rows, int cols, StatePlanes p, const DevState* st) {
   if (st->done) return;
   __shared__ T th[32][33], ts[32][33];
@@ -544,12 +543,13 @@ __device__ __forceinline__ unsigned split_word(double v) {
   return hb | (lb << 16);
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC, const T* HD,
-                                                         T* SC, const T* SD, int rows, int cols,
+template <typename T, typename TD>
+__global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC, const TD* HD,
+                                                         T* SC, const TD* SD, int rows, int cols,
                                                          StatePlanes p, const DevState* st) {
   if (st->done) return;
   typedef T T2 __attribute__((ext_vector_type(2)));
+  typedef TD TD2 __attribute__((ext_vector_type(2)));
   __shared__ unsigned th[64][65], ts[64][65];
   const double x = st->x;
   const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
@@ -559,7 +559,8 @@ __global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC
   constexpr int RB = 4;
 #pragma unroll
   for (int b = 0; b < 8; b += RB) {
-    T2 c[RB], d[RB], hc[RB], hd[RB], sc[RB], sd[RB];
+    T2 c[RB], d[RB], hc[RB], sc[RB];
+    TD2 hd[RB], sd[RB];
     bool in[RB];
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
@@ -570,9 +571,9 @@ __global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC
         c[k] = *reinterpret_cast<const T2*>(C + e);
         d[k] = *reinterpret_cast<const T2*>(D + e);
         hc[k] = *reinterpret_cast<const T2*>(HC + e);
-        hd[k] = *reinterpret_cast<const T2*>(HD + e);
+        hd[k] = *reinterpret_cast<const TD2*>(HD + e);
         sc[k] = *reinterpret_cast<const T2*>(SC + e);
-        sd[k] = *reinterpret_cast<const T2*>(SD + e);
+        sd[k] = *reinterpret_cast<const TD2*>(SD + e);
       }
     }
 #pragma unroll
@@ -875,30 +876,32 @@ hipError_t block_pattern(const double* B, int64_t n, unsigned char* flags, hipSt
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t beta_and_direction(const T* G, const T* PG, const T* Gprev, T* D, int64_t n, int first,
+template <typename T, typename TP>
+hipError_t beta_and_direction(const T* G, const TP* PG, const T* Gprev, T* D, int64_t n, int first,
                               double* partials, DevState* st, hipStream_t s, unsigned short* hi,
                               int64_t cols, int64_t ld) {
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_pr_partials<T>, dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first, partials,
-                     st);
+  hipLaunchKernelGGL((k_pr_partials<T, TP>), dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first,
+                     partials, st);
   hipLaunchKernelGGL(k_pr_final, dim3(1), dim3(NT), 0, s, partials, nb, first, st);
   if (hi) {
     if (cols <= 0 || n % cols != 0 || n / cols > 65535 || ld < cols) return hipErrorInvalidValue;
     int64_t bx = (cols + NT - 1) / NT;
-    hipLaunchKernelGGL(k_direction_bf16<T>, dim3((unsigned)bx, (unsigned)(n / cols)), dim3(NT), 0, s,
-                       PG, D, hi, cols, ld, first, st);
+    hipLaunchKernelGGL((k_direction_bf16<T, TP>), dim3((unsigned)bx, (unsigned)(n / cols)), dim3(NT),
+                       0, s, PG, D, hi, cols, ld, first, st);
   } else {
-    hipLaunchKernelGGL(k_direction<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, n, first, st);
+    hipLaunchKernelGGL((k_direction<T, TP>), dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, n, first, st);
   }
   return hipGetLastError();
 }
-template hipError_t beta_and_direction<double>(const double*, const double*, const double*,
-                                               double*, int64_t, int, double*, DevState*,
-                                               hipStream_t, unsigned short*, int64_t, int64_t);
-template hipError_t beta_and_direction<float>(const float*, const float*, const float*, float*,
-                                              int64_t, int, double*, DevState*, hipStream_t,
-                                              unsigned short*, int64_t, int64_t);
+#define OMM_BETA_DIRECTION(T, TP)                                                                \
+  template hipError_t beta_and_direction<T, TP>(const T*, const TP*, const T*, T*, int64_t, int,  \
+                                                double*, DevState*, hipStream_t, unsigned short*, \
+                                                int64_t, int64_t);
+OMM_BETA_DIRECTION(double, double)
+OMM_BETA_DIRECTION(float, float)
+OMM_BETA_DIRECTION(double, float)
+#undef OMM_BETA_DIRECTION
 
 hipError_t line_search(const double* HW, const double* SW, const double* H1, const double* S1,
                        const double* H2, const double* S2, int M, double* partials, DevState* st,
@@ -910,45 +913,46 @@ hipError_t line_search(const double* HW, const double* SW, const double* H1, con
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t update_coefficients(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD, int64_t n,
-                               const DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_mn<T>, dim3(ew_blocks(n)), dim3(NT), 0, s, C, D, HC, HD, SC, SD, n,
-                     st);
+template <typename T, typename TD>
+hipError_t update_coefficients(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD,
+                               int64_t n, const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL((k_update_mn<T, TD>), dim3(ew_blocks(n)), dim3(NT), 0, s, C, D, HC, HD, SC, SD,
+                     n, st);
   return hipGetLastError();
 }
-template hipError_t update_coefficients<double>(double*, const double*, double*, const double*,
-                                                double*, const double*, int64_t, const DevState*,
-                                                hipStream_t);
-template hipError_t update_coefficients<float>(float*, const float*, float*, const float*, float*,
-                                               const float*, int64_t, const DevState*,
-                                               hipStream_t);
+#define OMM_UPDATE(T, TD)                                                                        \
+  template hipError_t update_coefficients<T, TD>(T*, const T*, T*, const TD*, T*, const TD*,     \
+                                                 int64_t, const DevState*, hipStream_t);
+OMM_UPDATE(double, double)
+OMM_UPDATE(float, float)
+OMM_UPDATE(double, float)
+#undef OMM_UPDATE
 
-template <typename T>
-hipError_t update_coefficients_split(T* C, const T* D, T* HC, const T* HD, T* SC, const T* SD,
+template <typename T, typename TD>
+hipError_t update_coefficients_split(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD,
                                      int rows, int cols, const StatePlanes& p, const DevState* st,
                                      hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   if (p.ld < cols || p.ldt < rows) return hipErrorInvalidValue;
   const bool wide = cols % 2 == 0 && p.ld % 2 == 0 && p.ldt % 2 == 0 &&
-                    ((uintptr_t)C | (uintptr_t)D | (uintptr_t)HC | (uintptr_t)HD | (uintptr_t)SC |
-                     (uintptr_t)SD) % (2 * sizeof(T)) == 0;
+                    ((uintptr_t)C | (uintptr_t)D | (uintptr_t)HC | (uintptr_t)SC) % (2 * sizeof(T)) == 0 &&
+                    ((uintptr_t)HD | (uintptr_t)SD) % (2 * sizeof(TD)) == 0;
   if (wide)
-    hipLaunchKernelGGL(k_update_split_mn2<T>, dim3((cols + 63) / 64, (rows + 63) / 64), dim3(NT), 0,
-                       s, C, D, HC, HD, SC, SD, rows, cols, p, st);
+    hipLaunchKernelGGL((k_update_split_mn2<T, TD>), dim3((cols + 63) / 64, (rows + 63) / 64),
+                       dim3(NT), 0, s, C, D, HC, HD, SC, SD, rows, cols, p, st);
   else
-    hipLaunchKernelGGL(k_update_split_mn<T>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0,
-                       s, C, D, HC, HD, SC, SD, rows, cols, p, st);
+    hipLaunchKernelGGL((k_update_split_mn<T, TD>), dim3((cols + 31) / 32, (rows + 31) / 32),
+                       dim3(NT), 0, s, C, D, HC, HD, SC, SD, rows, cols, p, st);
   return hipGetLastError();
 }
-template hipError_t update_coefficients_split<double>(double*, const double*, double*,
-                                                      const double*, double*, const double*, int,
-                                                      int, const StatePlanes&, const DevState*,
-                                                      hipStream_t);
-template hipError_t update_coefficients_split<float>(float*, const float*, float*, const float*,
-                                                     float*, const float*, int, int,
-                                                     const StatePlanes&, const DevState*,
-                                                     hipStream_t);
+#define OMM_UPDATE_SPLIT(T, TD)                                                                  \
+  template hipError_t update_coefficients_split<T, TD>(T*, const T*, T*, const TD*, T*,          \
+                                                       const TD*, int, int, const StatePlanes&,  \
+                                                       const DevState*, hipStream_t);
+OMM_UPDATE_SPLIT(double, double)
+OMM_UPDATE_SPLIT(float, float)
+OMM_UPDATE_SPLIT(double, float)
+#undef OMM_UPDATE_SPLIT
 
 hipError_t update_subspace(double* HW, double* SW, const double* H1, const double* S1,
                            const double* H2, const double* S2, int M, double* partials,
