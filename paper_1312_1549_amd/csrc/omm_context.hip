@@ -861,6 +861,9 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
                      make_op2(M, M, N, Dop, bf ? pl(c->SC_p) : dn(w.SC, N), c->S1, M),
                      make_op2(M, M, N, Dop, bf ? pl(c->HD_p) : dn(w.HD, N), c->H2, M),
                      make_op2(M, M, N, Dop, bf ? pl(SD_p) : dn(SD, N), c->S2, M)};
+    // H'' = D Hs D^T and S'' = D S D^T are symmetric (Eq. 15): their upper block triangles are
+    // computed and mirrored
+    ops[2].tri = ops[3].tri = 1;
     TRY(gemm(c, d, ops, 4, done));
   }
   TRY(prof_mark(c));

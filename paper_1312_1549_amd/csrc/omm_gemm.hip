@@ -24,11 +24,34 @@ __global__ __launch_bounds__(256) void splitk_reduce(GemmBatch batch, const int*
   for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < mn;
        idx += (int64_t)gridDim.x * 256) {
     double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += ws[((int64_t)sp * nops + blockIdx.y) * mn + idx];
     const int row = (int)(idx / op.N), col = (int)(idx % op.N);
+    if (op.tri && row > col) continue;  // mirrored afterwards (its tile may not have run)
+    for (int sp = 0; sp < nsplit; ++sp) s += ws[((int64_t)sp * nops + blockIdx.y) * mn + idx];
     double v = op.alpha * s;
     if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
     store_out<TC>(op, row, col, v);
+  }
+}
+// C[i][j] = C[j][i] for i > j of every symmetric (tri) product: 32 x 32 blocks on and below the
+// diagonal, each read transposed through LDS from its mirror block.
+template <typename TC>
+__global__ __launch_bounds__(256) void mirror_lower(GemmBatch batch, const int* done) {
+  if (done && *done) return;
+  const GemmOp& op = batch.op[blockIdx.z];
+  if (!op.tri) return;
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;  // destination block (rows bi, cols bj)
+  if (bj > bi || bi >= op.M) return;
+  __shared__ TC t[32][33];
+  TC* C = static_cast<TC*>(op.C);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {  // source block: rows bj, cols bi
+    const int i = bj + r, j = bi + tx;
+    if (i < op.M && j < op.N) t[r][tx] = C[(int64_t)i * op.ldc + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi + r, j = bj + tx;
+    if (i < op.M && j < op.N && i > j) C[(int64_t)i * op.ldc + j] = t[tx][r];
   }
 }
 }  // namespace
@@ -99,8 +122,9 @@ hipError_t gemm_grouped_launch(const GemmDesc& d, const GemmOp* d_ops, const int
 int gemm_tile_rows(int tile, int mode) { return tile_bm(tile, mode); }
 int gemm_tile_cols(int tile, int mode) { return tile_bn(tile, mode); }
 
-hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int* done, double* ws,
-                       size_t ws_bytes, hipStream_t s) {
+namespace {
+hipError_t launch_products(const GemmDesc& d, const GemmOp* ops, int nops, const int* done,
+                           double* ws, size_t ws_bytes, hipStream_t s) {
   if (nops < 1 || nops > 4) return hipErrorInvalidValue;
   GemmBatch b;
   for (int i = 0; i < nops; ++i) {
@@ -127,14 +151,16 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
       sk_fn fn = pick_sk(dd);
       if (!fn || dd.splitk > 1) return hipErrorInvalidValue;
       if (!ws || ws_bytes < gemm_ws_bytes(dd, ops, nops)) return hipErrorInvalidValue;
-      const int tiles = ((M + DMA_BM - 1) / DMA_BM) * ((N + DMA_BN - 1) / DMA_BN);
+      int tiles = 0;  // tile-ops over all products
+      for (int i = 0; i < nops; ++i) tiles += op_tiles(ops[i], DMA_BM, DMA_BN);
       const int ktot = ops[0].K[0] + (ops[0].nseg > 1 ? ops[0].K[1] : 0);
       for (int i = 1; i < nops; ++i)
         if (ops[i].nseg != ops[0].nseg || ops[i].K[0] != ops[0].K[0] ||
             (ops[0].nseg > 1 && ops[i].K[1] != ops[0].K[1]))
           return hipErrorInvalidValue;  // one K schedule for every product of the launch
       SkArgs a;
-      a.T = tiles * nops;
+      a.T = tiles;
+      a.nops = nops;
       a.nk = (ktot + DMA_BK - 1) / DMA_BK;
       a.R = a.T / SK_GRID;
       a.W = (int64_t)(a.T - a.R * SK_GRID) * a.nk;
@@ -176,6 +202,28 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
   if (dd.tc == T_F64) red = dd.tx == T_F64 ? splitk_reduce<double, double> : splitk_reduce<double, float>;
   else red = dd.tx == T_F64 ? splitk_reduce<float, double> : splitk_reduce<float, float>;
   hipLaunchKernelGGL(red, rgrid, dim3(256), 0, s, b, done, splitk, (const double*)ws);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int* done, double* ws,
+                       size_t ws_bytes, hipStream_t s) {
+  if (nops < 1 || nops > 4) return hipErrorInvalidValue;
+  bool tri = false;
+  for (int i = 0; i < nops; ++i) {
+    if (!ops[i].tri) continue;
+    if (ops[i].M != ops[i].N || ops[i].Chi || ops[i].kptr) return hipErrorInvalidValue;
+    tri = true;
+  }
+  hipError_t e = launch_products(d, ops, nops, done, ws, ws_bytes, s);
+  if (e != hipSuccess || !tri || ops[0].M <= 0) return e;
+  GemmBatch b;
+  for (int i = 0; i < nops; ++i) b.op[i] = ops[i];
+  const int nb = (ops[0].M + 31) / 32;
+  if (d.tc == T_F64)
+    hipLaunchKernelGGL(mirror_lower<double>, dim3(nb, nb, nops), dim3(256), 0, s, b, done);
+  else
+    hipLaunchKernelGGL(mirror_lower<float>, dim3(nb, nb, nops), dim3(256), 0, s, b, done);
   return hipGetLastError();
 }
 

@@ -75,6 +75,26 @@ __device__ __forceinline__ bool tile_of(int tiles_m, int tiles_n, int& tm, int& 
   return true;
 }
 
+// Tiles an op computes (bm x bn macro tiles): all of them, or for a symmetric (tri) op the
+// tiles with tm <= tn. op_tile maps an index in [0, op_tiles) to (tm, tn): M fastest, and for
+// a tri op column tn holds tm = 0 .. tn.
+__host__ __device__ __forceinline__ int op_tiles(const GemmOp& op, int bm, int bn) {
+  const int tm = (op.M + bm - 1) / bm, tn = (op.N + bn - 1) / bn;
+  return op.tri ? tn * (tn + 1) / 2 : tm * tn;
+}
+__device__ __forceinline__ void op_tile(const GemmOp& op, int bm, int t, int& tm, int& tn) {
+  if (op.tri) {
+    int c = 0;
+    while ((c + 1) * (c + 2) / 2 <= t) ++c;
+    tn = c;
+    tm = t - c * (c + 1) / 2;
+  } else {
+    const int tiles_m = (op.M + bm - 1) / bm;
+    tm = t % tiles_m;
+    tn = t / tiles_m;
+  }
+}
+
 // K range [kb, ke) of segment `seg` owned by split `sp` (splits cut the concatenated K of all
 // segments into BK-aligned chunks).
 template <int BK>
@@ -558,6 +578,7 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
 // of 8, and a first segment length that is a multiple of 8 (checked by the launcher).
 constexpr int DMA_BM = 256, DMA_BN = 256, DMA_BK = 32, DMA_PLANE = DMA_BM * DMA_BK;
 static_assert(DMA_BN == SPARSE_BN && DMA_BK == SPARSE_BK, "block-sparse lists follow this tile");
+static_assert(DMA_BM == DMA_BN, "op_tiles / op_tile enumerate symmetric products on square tiles");
 
 // s_waitcnt: vmcnt <= n, lgkmcnt = 0 (expcnt unconstrained)
 template <int N>
@@ -759,6 +780,7 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_dma(GemmBatch batch, const
   const int tiles_m = (op.M + DMA_BM - 1) / DMA_BM, tiles_n = (op.N + DMA_BN - 1) / DMA_BN;
   int tm, tn;
   if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
+  if (op.tri && tm > tn) return;  // square tiles: wholly below the diagonal, mirrored
   const int ktot = op.K[0] + (op.nseg > 1 ? op.K[1] : 0);
   const int nk = (ktot + DMA_BK - 1) / DMA_BK;
   const int per = (nk + nsplit - 1) / nsplit;
@@ -788,7 +810,21 @@ struct SkArgs {
   int nk;      // K steps per tile
   int R;       // data-parallel rounds
   int64_t W;   // K steps of the cut tile-ops
+  int nops;    // products in the launch (tile-ops run through them in order)
 };
+
+// Product and tile of tile-op `to` (the products' tile lists concatenated in order).
+__device__ __forceinline__ const GemmOp* sk_locate(const GemmBatch& b, int nops, int to, int& tm,
+                                                   int& tn) {
+  int z = 0;
+  for (; z + 1 < nops; ++z) {
+    const int c = op_tiles(b.op[z], DMA_BM, DMA_BN);
+    if (to < c) break;
+    to -= c;
+  }
+  op_tile(b.op[z], DMA_BM, to, tm, tn);
+  return &b.op[z];
+}
 
 __device__ __forceinline__ int64_t sk_bound(int64_t W, int h, int G) { return W * h / G; }
 
@@ -799,17 +835,9 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_sk(GemmBatch batch, const 
   const int G = gridDim.x, g = blockIdx.x;
   const int h = (g & 7) * (G >> 3) + (g >> 3);
   const GemmOp& op0 = batch.op[0];
-  const int tiles_m = (op0.M + DMA_BM - 1) / DMA_BM, tiles_n = (op0.N + DMA_BN - 1) / DMA_BN;
-  const int per_op = tiles_m * tiles_n;
   const int ktot = op0.K[0] + (op0.nseg > 1 ? op0.K[1] : 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   f4 acc[DMA_TM][DMA_TN];
-  auto locate = [&](int to, const GemmOp*& op, int& tm, int& tn) {
-    const int z = to / per_op, t = to % per_op;
-    op = &batch.op[z];
-    tm = t % tiles_m;
-    tn = t / tiles_m;
-  };
   // One loop over this workgroup's work items (one call site of the tile loop and of the
   // epilogue): first the data-parallel rounds (whole tiles), then its share [u0, u1) of the K
   // steps of the cut tiles.
@@ -830,9 +858,8 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_sk(GemmBatch batch, const 
       k1 = (int)min((int64_t)a.nk, k0 + (u1 - u));
       u += k1 - k0;
     }
-    const GemmOp* op;
     int tm, tn;
-    locate(to, op, tm, tn);
+    const GemmOp* op = sk_locate(batch, a.nops, to, tm, tn);
     gemm_tile_dma_acc<MODE, NS, DmaUser<1, TC>>(*op, tm, tn, k0 * DMA_BK, min(ktot, k1 * DMA_BK),
                                                 acc);
     if (k0 == 0 && k1 == a.nk) {
@@ -885,12 +912,8 @@ __global__ __launch_bounds__(256) void gemm_sk_fixup(GemmBatch batch, const int*
   __syncthreads();
   const int n = nslot;
   if (n == 0) return;
-  const GemmOp& op0 = batch.op[0];
-  const int tiles_m = (op0.M + DMA_BM - 1) / DMA_BM, tiles_n = (op0.N + DMA_BN - 1) / DMA_BN;
-  const int per_op = tiles_m * tiles_n;
-  const int to = a.R * G + q, z = to / per_op, t = to % per_op;
-  const GemmOp& op = batch.op[z];
-  const int tm = t % tiles_m, tn = t / tiles_m;
+  int tm, tn;
+  const GemmOp& op = *sk_locate(batch, a.nops, a.R * G + q, tm, tn);
   constexpr int PER = DMA_BM * DMA_BN / SK_FIX_CHUNKS;
   for (int f = blockIdx.y * PER + threadIdx.x; f < (blockIdx.y + 1) * PER; f += 256) {
     // the parts are added in K order; four loads are in flight at a time
@@ -928,6 +951,8 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch
   const int tiles_m = (op.M + BM - 1) / BM, tiles_n = (op.N + BN - 1) / BN;
   int tm, tn;
   if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
+  // symmetric result: a tile wholly below the diagonal (first row > last column) is mirrored
+  if (op.tri && tm * BM > tn * BN + BN - 1) return;
   gemm_tile<MODE, TA, TB, TC, TX, LA, LB, WM, WN, TM, TN, BK, SWZ>(op, tm, tn, blockIdx.y, nsplit,
                                                                   ws, blockIdx.z, gridDim.z);
 }

@@ -64,6 +64,9 @@ struct GemmOp {
   void* Chi;
   void* Clo;
   int64_t ldp;
+  // Symmetric result (M == N, no planes): only the tiles on and above the diagonal are computed
+  // and the launcher then copies C[j][i] into C[i][j] for every i > j.
+  int tri;
 };
 
 struct GemmDesc {

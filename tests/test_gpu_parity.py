@@ -284,6 +284,19 @@ def test_fused_planes_match_separate_splits(lib_ok, c2, tile, refine, monkeypatc
     assert np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("tile", ["0", "2", "3"])
+def test_symmetric_projections_on_every_tile_shape(lib_ok, c2, tile, monkeypatch):
+    """H'' and S'' (Eq. 15) are computed on their upper block triangle and mirrored. With square
+    (128 x 128) and non-square (256 x 128, 128 x 256) macro tiles pinned, the FP64 trajectory at
+    config 2 still follows the oracle's line search for line search."""
+    s, C0, _ = c2
+    monkeypatch.setenv("OMM_TILE", tile)
+    _say(f"symmetric projections, fp64 c2, tile {tile}")
+    solver, _ = _run(lib_ok, s, C0, 0.5, 10.0, 0.0, 8)
+    ref = oracle.minimize(s.H, s.S, s.T, C0, 0.5, 10.0, 0.0, 8)
+    np.testing.assert_allclose(solver.energy_trace(), ref.energies, rtol=1e-11, atol=0)
+
+
 def test_fully_occupied_limit(lib_ok):
     """M = N: every eigenvector is occupied; with eta above the whole spectrum the minimum is
     2 sum_i (eps_i - eta) and SW = I (C^T C = S^-1 in row form)."""
