@@ -979,7 +979,7 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_grouped_kernel(Grouped
     }
     const int* dn = g.done[lo];
     if (dn && *dn) continue;
-    const GemmOp op = g.ops[lo];
+    const GemmOp& op = g.ops[lo];  // by reference: a local copy would sit in scratch memory
     const int tiles_m = (op.M + BM - 1) / BM;
     const int local = t - g.tile_start[lo];
     gemm_tile<MODE, TA, TB, TC, TX, LA, LB, WM, WN, TM, TN, BK, SWZ>(
