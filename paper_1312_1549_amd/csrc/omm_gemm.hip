@@ -82,6 +82,9 @@ bool dma_ok(const GemmDesc& d, const GemmOp* ops, int nops) {
     if (op.nseg == 2 && op.K[0] % 8 != 0) return false;
     for (int g = 0; g < op.nseg; ++g) {
       if (op.lda[g] % 8 != 0 || op.ldb[g] % 8 != 0) return false;
+      // lane addresses are 32-bit byte offsets from the plane base
+      constexpr int64_t lim = (int64_t)1 << 31;
+      if ((int64_t)op.M * op.lda[g] >= lim || (int64_t)op.N * op.ldb[g] >= lim) return false;
       if (!al(op.A[g]) || !al(op.B[g])) return false;
       if (d.compute != CBF16X2A && !al(op.Alo[g])) return false;
       if (d.compute != CBF16X2B && !al(op.Blo[g])) return false;

@@ -115,7 +115,7 @@ hipError_t shift_hamiltonian(const double* H, const double* S, double eta, doubl
                              hipStream_t s);
 hipError_t convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 // hi = bf16(x), lo = bf16(x - hi) (round to nearest even), skipped when st->done. src is rows x
-// cols (contiguous); hi/lo rows have length ld (>= cols, a multiple of 4; rows <= 65535).
+// cols (contiguous); hi/lo rows have length ld (>= cols, a multiple of 4).
 hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, int64_t rows,
                       int64_t cols, int64_t ld, const DevState* st, hipStream_t s);
 hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t rows,

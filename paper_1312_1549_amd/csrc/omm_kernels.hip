@@ -59,33 +59,35 @@ __device__ __forceinline__ unsigned short bf16_bits(float f) {
 }
 
 // hi/lo bf16 planes of src (rows x cols, contiguous) into rows of length ld >= cols (ld a
-// multiple of 4): one row per blockIdx.y, 4 elements per thread (8-byte stores).
+// multiple of 4): rows blockIdx.y, blockIdx.y + gridDim.y, .., 4 elements per thread (8-byte
+// stores).
 template <typename T>
-__global__ void k_split(const T* src, unsigned short* hi, unsigned short* lo, int64_t cols,
-                        int64_t ld, const DevState* st) {
+__global__ void k_split(const T* src, unsigned short* hi, unsigned short* lo, int64_t rows,
+                        int64_t cols, int64_t ld, const DevState* st) {
   if (st && st->done) return;
   typedef unsigned short us4 __attribute__((ext_vector_type(4)));
-  const int64_t r = blockIdx.y;
-  const T* srow = src + r * cols;
-  for (int64_t c4 = ((int64_t)blockIdx.x * NT + threadIdx.x) * 4; c4 < cols;
-       c4 += (int64_t)gridDim.x * NT * 4) {
-    if (c4 + 4 <= cols) {
-      us4 h, l;
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+    const T* srow = src + r * cols;
+    for (int64_t c4 = ((int64_t)blockIdx.x * NT + threadIdx.x) * 4; c4 < cols;
+         c4 += (int64_t)gridDim.x * NT * 4) {
+      if (c4 + 4 <= cols) {
+        us4 h, l;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double v = (double)srow[c4 + u];
-        const unsigned short hb = bf16_bits((float)v);
-        h[u] = hb;
-        l[u] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
-      }
-      *reinterpret_cast<us4*>(hi + r * ld + c4) = h;
-      *reinterpret_cast<us4*>(lo + r * ld + c4) = l;
-    } else {
-      for (int64_t c = c4; c < cols; ++c) {
-        const double v = (double)srow[c];
-        const unsigned short hb = bf16_bits((float)v);
-        hi[r * ld + c] = hb;
-        lo[r * ld + c] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+        for (int u = 0; u < 4; ++u) {
+          const double v = (double)srow[c4 + u];
+          const unsigned short hb = bf16_bits((float)v);
+          h[u] = hb;
+          l[u] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+        }
+        *reinterpret_cast<us4*>(hi + r * ld + c4) = h;
+        *reinterpret_cast<us4*>(lo + r * ld + c4) = l;
+      } else {
+        for (int64_t c = c4; c < cols; ++c) {
+          const double v = (double)srow[c];
+          const unsigned short hb = bf16_bits((float)v);
+          hi[r * ld + c] = hb;
+          lo[r * ld + c] = bf16_bits((float)(v - (double)__uint_as_float(((unsigned int)hb) << 16)));
+        }
       }
     }
   }
@@ -295,18 +297,19 @@ __global__ void k_direction(const TP* PG, T* D, int64_t n, int first, const DevS
 // bits (rows of length ld), so the products with D need no lo plane and the CG update moves along
 // exactly this D. One row of D (rows x cols) per blockIdx.y.
 template <typename T, typename TP>
-__global__ void k_direction_bf16(const TP* PG, T* D, unsigned short* hi, int64_t cols, int64_t ld,
-                                 int first, const DevState* st) {
+__global__ void k_direction_bf16(const TP* PG, T* D, unsigned short* hi, int64_t rows, int64_t cols,
+                                 int64_t ld, int first, const DevState* st) {
   if (st->done) return;
   const double beta = st->beta;
-  const int64_t r = blockIdx.y;
-  for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < cols; c += (int64_t)gridDim.x * NT) {
-    const int64_t i = r * cols + c;
-    const double d = first ? -(double)PG[i] : -(double)PG[i] + beta * (double)D[i];
-    const unsigned short hb = bf16_bits((float)d);
-    hi[r * ld + c] = hb;
-    D[i] = (T)__uint_as_float(((unsigned int)hb) << 16);
-  }
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
+    for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < cols;
+         c += (int64_t)gridDim.x * NT) {
+      const int64_t i = r * cols + c;
+      const double d = first ? -(double)PG[i] : -(double)PG[i] + beta * (double)D[i];
+      const unsigned short hb = bf16_bits((float)d);
+      hi[r * ld + c] = hb;
+      D[i] = (T)__uint_as_float(((unsigned int)hb) << 16);
+    }
 }
 
 // ---- quartic coefficients (Eq. 13) --------------------------------------------------------------
@@ -799,25 +802,25 @@ namespace {
 dim3 split_grid(int64_t rows, int64_t cols) {
   int64_t bx = (cols + 4 * NT - 1) / (4 * NT);
   if (bx < 1) bx = 1;
-  return dim3((unsigned)bx, (unsigned)rows);
+  return dim3((unsigned)bx, (unsigned)(rows < 65535 ? rows : 65535));
 }
 }  // namespace
 
 hipError_t split_bf16(const float* src, unsigned short* hi, unsigned short* lo, int64_t rows,
                       int64_t cols, int64_t ld, const DevState* st, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  if (rows > 65535 || ld < cols || ld % 4 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_split<float>, split_grid(rows, cols), dim3(NT), 0, s, src, hi, lo, cols, ld,
-                     st);
+  if (ld < cols || ld % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split<float>, split_grid(rows, cols), dim3(NT), 0, s, src, hi, lo, rows, cols,
+                     ld, st);
   return hipGetLastError();
 }
 
 hipError_t split_bf16(const double* src, unsigned short* hi, unsigned short* lo, int64_t rows,
                       int64_t cols, int64_t ld, const DevState* st, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  if (rows > 65535 || ld < cols || ld % 4 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_split<double>, split_grid(rows, cols), dim3(NT), 0, s, src, hi, lo, cols, ld,
-                     st);
+  if (ld < cols || ld % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split<double>, split_grid(rows, cols), dim3(NT), 0, s, src, hi, lo, rows,
+                     cols, ld, st);
   return hipGetLastError();
 }
 
@@ -885,10 +888,10 @@ hipError_t beta_and_direction(const T* G, const TP* PG, const T* Gprev, T* D, in
                      partials, st);
   hipLaunchKernelGGL(k_pr_final, dim3(1), dim3(NT), 0, s, partials, nb, first, st);
   if (hi) {
-    if (cols <= 0 || n % cols != 0 || n / cols > 65535 || ld < cols) return hipErrorInvalidValue;
-    int64_t bx = (cols + NT - 1) / NT;
-    hipLaunchKernelGGL((k_direction_bf16<T, TP>), dim3((unsigned)bx, (unsigned)(n / cols)), dim3(NT),
-                       0, s, PG, D, hi, cols, ld, first, st);
+    if (cols <= 0 || n % cols != 0 || ld < cols) return hipErrorInvalidValue;
+    const int64_t rows = n / cols, bx = (cols + NT - 1) / NT;
+    hipLaunchKernelGGL((k_direction_bf16<T, TP>), dim3((unsigned)bx, (unsigned)(rows < 65535 ? rows : 65535)),
+                       dim3(NT), 0, s, PG, D, hi, rows, cols, ld, first, st);
   } else {
     hipLaunchKernelGGL((k_direction<T, TP>), dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, n, first, st);
   }
