@@ -49,8 +49,9 @@ def reference_energy(name, s):
     if not f.exists():
         return None
     d = json.loads(f.read_text())
-    if abs(d["trace_H"] - float(np.trace(s.H))) > 1e-9 * abs(d["trace_H"]) or \
-            abs(d["sum_S"] - float(np.sum(s.S))) > 1e-9 * abs(d["sum_S"]):
+    tr, sm = float(np.real(np.trace(s.H))), float(np.real(np.sum(s.S)))
+    if abs(d["trace_H"] - tr) > 1e-9 * abs(d["trace_H"]) or \
+            abs(d["sum_S"] - sm) > 1e-9 * abs(d["sum_S"]):
         return None
     return float(d["E_min"])
 
@@ -136,6 +137,84 @@ def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, resync,
            "checked_every": resync}
     if mixed:
         out["resync_every"] = resync
+    return out
+
+
+def complex_bench(args, torch):
+    """Complex Hermitian problems (k-points) through OMMComplex / OMMBatchComplex: the config-5
+    lattice made periodic along x at k = 0.3 (complex N = 4096, M = 768; real embedding 8192 x
+    1536), BF16-scheme and FP64 rates and time to 1e-8 of the closed form; and a batch of four
+    config-2 k-points (FP32 grouped launches) solved to tol 1e-10."""
+    from paper_1312_1549_amd import OMMBatchComplex, OMMComplex
+    from synth import bloch_system, complex_start_coefficients
+
+    k = 0.3
+    log(f"complex: generating c5 at k={k}")
+    s = bloch_system("c5", k, 0)
+    C0 = complex_start_coefficients(s.S, s.M, 1)
+    out = {"workload": f"config-5 lattice (16x8x8, a=2.5, rc=6) periodic along x, k={k}: complex "
+                       f"N={s.N}, M={s.M} (real embedding {2 * s.N} x {2 * s.M})",
+           "eta": s.eta, "tau": s.tau}
+
+    def solver_for(prec):
+        sol = OMMComplex(s.N, s.M, precision=prec, refine=True, resync=args.resync)
+        sol.set_HS(s.H, s.S, s.T)
+        sol.minimize(C0, eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)
+        torch.cuda.synchronize()
+        return sol
+
+    for prec, steps in (("bf16x3", args.steps), ("fp64", max(3, args.steps // 4))):
+        sol = solver_for(prec)
+        sol.iterate(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol.iterate(steps)
+        torch.cuda.synchronize()
+        out[f"{prec}_iters_per_s"] = steps / (time.perf_counter() - t0)
+        sol.close()
+        log(f"complex {prec}: {out[prec + '_iters_per_s']:.2f} iters/s")
+    E_ref = reference_energy("c5_k0.3", s)
+    if E_ref is not None and not args.no_converge:
+        conv = {}
+        for prec in ("bf16x3", "fp64"):
+            sol = solver_for(prec)
+            t0 = time.perf_counter()
+            sol.minimize(C0, eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)
+            done, hit, err = 0, None, float("inf")
+            while done < args.max_iter:
+                sol.iterate(args.resync, tol=0.0)
+                done += args.resync
+                E = sol.checkpoints()[1][-1] if prec != "fp64" else sol.energy_trace()[-1]
+                err = abs(E - E_ref) / abs(E_ref)
+                if err <= 1e-8:
+                    hit = done
+                    break
+            torch.cuda.synchronize()
+            conv[prec] = {"line_searches": hit, "time_to_target_s": time.perf_counter() - t0 if hit
+                          else None, "rel_err_at_stop": err, "checked_every": args.resync}
+            sol.close()
+            log(f"complex {prec}: 1e-8 after {hit} line searches")
+        conv["E_ref"] = E_ref
+        out["time_to_converged_1e-8"] = conv
+    # a k-point batch: four k-points of config 2 solved together
+    ks = (0.0, 0.1, 0.2, 0.3)
+    log("complex: k-point batch, config 2 x 4")
+    systems = [bloch_system("c2", kk, 0) for kk in ks]
+    b = OMMBatchComplex([x.N for x in systems], [x.M for x in systems])
+    for i, x in enumerate(systems):
+        b.set_HS(i, x.H, x.S, x.T)
+    C0s = [complex_start_coefficients(x.S, x.M, 10 + i) for i, x in enumerate(systems)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.minimize(C0s, [x.eta for x in systems], [x.tau for x in systems], 1e-10, 5000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    its = b.iterations()
+    out["kpoint_batch"] = {"workload": f"config 2 (complex N=2048, M=384) at k = {list(ks)}",
+                           "line_searches": int(its.sum()), "wall_s": wall,
+                           "line_searches_per_s": float(its.sum()) / wall,
+                           "precision": "fp32 products, fp64 reductions"}
+    b.close()
     return out
 
 
@@ -256,6 +335,8 @@ def main():
                     help="skip the Cholesky-reduced flavour's rate and time to converged")
     ap.add_argument("--no-sparse", action="store_true",
                     help="skip the block-sparse operator products' rate and time to converged")
+    ap.add_argument("--no-complex", action="store_true",
+                    help="skip the complex Hermitian (k-point) rates and time to converged")
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--resync", type=int, default=80)
     ap.add_argument("--cpu-iters", type=int, default=2)
@@ -390,6 +471,9 @@ def main():
                         args.resync, flavour="cholesky")
             conv["E_ref"] = E_ref
             result["time_to_converged"] = conv
+
+    if not args.no_complex and args.workload == "c3":
+        result["complex_kpoints"] = complex_bench(args, torch)
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_iters} oracle iterations")

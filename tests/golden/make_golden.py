@@ -2,7 +2,9 @@
 
 Calls only the oracle (its LAPACK-based closed form) and the seeded input generator:
 E_min = 2 sum_{i<=M} min(eps_i - eta, 0) over the lowest generalized eigenvalues of (H, S).
-Usage: python tests/golden/make_golden.py c3 [c2 c5 ...]
+A name of the form <workload>@k<value> (for example c5@k0.3) takes the complex Hermitian
+H(k), S(k) of that workload made periodic along x (synth.bloch_system).
+Usage: python tests/golden/make_golden.py c3 [c2 c5 c5@k0.3 ...]
 """
 
 import json
@@ -16,23 +18,29 @@ ROOT = Path(__file__).resolve().parents[2]
 sys.path.insert(0, str(ROOT))
 
 from oracle import brute  # noqa: E402
-from synth import config_system  # noqa: E402
+from synth import bloch_system, config_system  # noqa: E402
 
 
 def main(names):
     for name in names:
         t0 = time.time()
-        s = config_system(name, 0)
+        if "@k" in name:
+            base, k = name.split("@k")
+            s = bloch_system(base, float(k), 0)
+        else:
+            s = config_system(name, 0)
         w = brute.generalized_eigh_lapack(s.H, s.S, count=s.M + 1)[0]
         E = brute.closed_form_energy(w, s.M, s.eta)
         out = {
             "workload": name, "N": s.N, "M": s.M, "eta": s.eta, "tau": s.tau, "seed": 0,
             "E_min": E, "eps_M": float(w[s.M - 1]), "eps_M1": float(w[s.M]),
             "gap": float(w[s.M] - w[s.M - 1]), "eps_1": float(w[0]),
-            "trace_H": float(np.trace(s.H)), "sum_S": float(np.sum(s.S)), "shift": s.shift,
+            "trace_H": float(np.real(np.trace(s.H))), "sum_S": float(np.real(np.sum(s.S))),
+            "shift": s.shift,
             "source": "oracle.brute.closed_form_energy over LAPACK generalized eigenvalues",
         }
-        (Path(__file__).parent / f"{name}_reference.json").write_text(json.dumps(out, indent=1) + "\n")
+        fname = name.replace("@", "_")
+        (Path(__file__).parent / f"{fname}_reference.json").write_text(json.dumps(out, indent=1) + "\n")
         print(name, E, f"{time.time() - t0:.1f}s", flush=True)
 
 
