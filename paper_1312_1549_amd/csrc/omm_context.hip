@@ -692,6 +692,25 @@ int split_state(omm_ctx* c, const T* HC, const T* SC, bool check_done = true) {
   return OMM_OK;
 }
 
+// Complex problems on the real embedding: C = E(C_c) has row pairs [Re c, Im c], [-Im c, Re c],
+// and so does every product whose rows follow C's (E(X) E(Y) = E(X Y), E(X)^T = E(X^H)). Such a
+// product is computed for its first Mc rows and the other Mc filled by the pair rotation. Not
+// in the Cholesky flavour: the real Cholesky factor of E(S) is not an embedding, so C~ = C L has
+// no row pairs. Returns Mc, or 0 when every row is computed.
+int paired_rows(omm_ctx* c) { return c->cplx && !reduced(c) ? (int)c->Mc : 0; }
+
+// The second half of the rows of a paired product X (rows x cols, row length ld; type FP64 or
+// FP32) and of its optional planes.
+int fill_pairs(omm_ctx* c, void* X, int type, int64_t ld, int64_t cols, const Plane* p,
+               bool check_done = true) {
+  const int rh = paired_rows(c);
+  if (!rh) return OMM_OK;
+  HIPCHK(c, pair_rows(X, type == T_F64, ld, p ? p->hi : nullptr, p ? p->lo : nullptr,
+                      p ? p->ld : 0, rh, (int)(cols / 2), check_done ? c->st : nullptr,
+                      c->stream));
+  return OMM_OK;
+}
+
 // Initial products of a phase (Sec. 2.1, Eqs. 5-6; Sec. 2.3 footnote):
 //   [HC | SC] = C [Hs | S], HW = HC C^T, SW = SC C^T, E_0.
 // Hs, S are symmetric, so both products read k-contiguous rows (KC x KC).
@@ -706,20 +725,25 @@ int initial_products(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* 
     TRY(split(c, w.C, c->C_p, M, N, false));
   }
   const Opnd Cop = bf ? pl(c->C_p) : dn(w.C, N);
+  const int Mo = paired_rows(c) ? paired_rows(c) : M;  // rows computed by each product
   GemmDesc d{compute, et, et, elem_type<T>(), elem_type<T>(), KC, KC, 0, 1};
-  GemmOp ops[2] = {make_op2(M, N, N, Cop, bf ? pl(c->Hs_p) : dn(Hs, N), w.HC, N),
-                   make_op2(M, N, N, Cop, bf ? pl(c->S_p) : dn(S, N), w.SC, N)};
+  GemmOp ops[2] = {make_op2(Mo, N, N, Cop, bf ? pl(c->Hs_p) : dn(Hs, N), w.HC, N),
+                   make_op2(Mo, N, N, Cop, bf ? pl(c->S_p) : dn(S, N), w.SC, N)};
   // reduced problem (S~ = I): SC = C, kept as its own copy, which every update then moves
   // exactly like C
   const bool sid = reduced(c);
   TRY(gemm(c, d, ops, sid ? 1 : 2, nullptr));
+  TRY(fill_pairs(c, w.HC, elem_type<T>(), N, N, nullptr, false));
+  if (!sid) TRY(fill_pairs(c, w.SC, elem_type<T>(), N, N, nullptr, false));
   if (sid)
     HIPCHK(c, hipMemcpyAsync(w.SC, w.C, mn * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
   if (bf) TRY(split_state(c, w.HC, w.SC, false));
   GemmDesc d2{compute, et, et, T_F64, T_F64, KC, KC, 0, 1};
-  GemmOp ops2[2] = {make_op2(M, M, N, bf ? pl(c->HC_p) : dn(w.HC, N), Cop, c->HW, M),
-                    make_op2(M, M, N, bf ? pl(c->SC_p) : dn(w.SC, N), Cop, c->SW, M)};
+  GemmOp ops2[2] = {make_op2(Mo, M, N, bf ? pl(c->HC_p) : dn(w.HC, N), Cop, c->HW, M),
+                    make_op2(Mo, M, N, bf ? pl(c->SC_p) : dn(w.SC, N), Cop, c->SW, M)};
   TRY(gemm(c, d2, ops2, 2, nullptr));
+  TRY(fill_pairs(c, c->HW, T_F64, M, M, nullptr, false));
+  TRY(fill_pairs(c, c->SW, T_F64, M, M, nullptr, false));
   HIPCHK(c, energy_init(c->HW, c->SW, M, c->partials, c->st, trace, c->stream));
   return OMM_OK;
 }
@@ -769,6 +793,7 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   // BF16: the operand planes of G, HD, SD come from the GEMM epilogues and those of HC, SC from
   // the update kernel; OMM_FUSE=0 splits them in separate passes instead (same values)
   const bool fuse = bf && fuse_enabled();
+  const int Mo = paired_rows(c) ? paired_rows(c) : M;  // rows computed by each product
   const int et = elem_type<T>();
   const int ot = bf ? T_BF16P : et;  // operand element type of the GEMMs
   const int* done = &c->st->done;
@@ -783,8 +808,8 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     }
     // BF16x3 reads the transposed planes of SC, HC (k-contiguous); the others read SC, HC by rows
     GemmDesc d{compute, bf ? T_BF16P : T_F64, ot, et, et, KC, bf ? KC : RC, 0, 1};
-    GemmOp op = make_op2(M, N, M, bf ? pl(c->HW_p) : dn(c->HW, M), bf ? pl(c->SCt_p) : dn(w.SC, N),
-                         G, N, -4.0, w.HC, N, 8.0);
+    GemmOp op = make_op2(Mo, N, M, bf ? pl(c->HW_p) : dn(c->HW, M),
+                         bf ? pl(c->SCt_p) : dn(w.SC, N), G, N, -4.0, w.HC, N, 8.0);
     const Opnd a2 = bf ? pl(c->SW_p) : dn(c->SW, M), b2 = bf ? pl(c->HCt_p) : dn(w.HC, N);
     op.nseg = 2;
     op.A[1] = a2.p; op.Alo[1] = a2.lo; op.lda[1] = a2.ld;
@@ -793,6 +818,7 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     // G's planes for the preconditioner product, from the epilogue
     if (fuse && c->p_kind > 0) out_planes(op, c->G_p);
     TRY(gemm(c, d, &op, 1, done));
+    TRY(fill_pairs(c, G, et, N, N, fuse && c->p_kind > 0 ? &c->G_p : nullptr));
   }
   TRY(prof_mark(c));
   // BF16x3: the preconditioner is applied as its bf16 rounding (the hi plane of P, a symmetric
@@ -807,9 +833,10 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     if (bf && !fuse) TRY(split(c, G, c->G_p, M, N));
     const int tp = f32p ? T_F32 : et;
     GemmDesc d{cP, ot, ot, tp, tp, KC, KC, 0, 1};
-    GemmOp op = make_op2(M, N, N, bf ? pl(c->G_p) : dn(G, N), bf ? pl(c->P_p) : dn(P, N),
+    GemmOp op = make_op2(Mo, N, N, bf ? pl(c->G_p) : dn(G, N), bf ? pl(c->P_p) : dn(P, N),
                          f32p ? (void*)w.PGf : (void*)w.PG, N);
     TRY(gemm(c, d, &op, 1, done));
+    TRY(fill_pairs(c, f32p ? (void*)w.PGf : (void*)w.PG, tp, N, N, nullptr));
     PG = w.PG;
   }
   TRY(prof_mark(c));
@@ -828,9 +855,9 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   {
     const int td = hdf ? T_F32 : et;
     GemmDesc d{cD, ot, ot, td, td, KC, KC, 0, 1};
-    GemmOp ops[2] = {make_op2(M, N, N, Dop, bf ? pl(c->Hs_p) : dn(Hs, N),
+    GemmOp ops[2] = {make_op2(Mo, N, N, Dop, bf ? pl(c->Hs_p) : dn(Hs, N),
                               hdf ? (void*)w.HDf : (void*)w.HD, N),
-                     make_op2(M, N, N, Dop, bf ? pl(c->S_p) : dn(S, N),
+                     make_op2(Mo, N, N, Dop, bf ? pl(c->S_p) : dn(S, N),
                               hdf ? (void*)w.SDf : (void*)w.SD, N)};
     if (bf && sparse_products(c)) {
       for (int i = 0; i < 2; ++i) {
@@ -843,6 +870,8 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
       out_planes(ops[1], c->SD_p);
     }
     TRY(gemm(c, d, ops, sid ? 1 : 2, done));
+    TRY(fill_pairs(c, ops[0].C, td, N, N, fuse ? &c->HD_p : nullptr));
+    if (!sid) TRY(fill_pairs(c, ops[1].C, td, N, N, fuse ? &c->SD_p : nullptr));
   }
   TRY(prof_mark(c));
   if (bf && !fuse) {  // the projection stage's operand planes (D's lo plane stays zero)
@@ -857,14 +886,15 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   const Plane& SD_p = sid ? c->D_p : c->SD_p;
   {
     GemmDesc d{cD, ot, ot, T_F64, T_F64, KC, KC, 0, 1};
-    GemmOp ops[4] = {make_op2(M, M, N, Dop, bf ? pl(c->HC_p) : dn(w.HC, N), c->H1, M),
-                     make_op2(M, M, N, Dop, bf ? pl(c->SC_p) : dn(w.SC, N), c->S1, M),
-                     make_op2(M, M, N, Dop, bf ? pl(c->HD_p) : dn(w.HD, N), c->H2, M),
-                     make_op2(M, M, N, Dop, bf ? pl(SD_p) : dn(SD, N), c->S2, M)};
+    GemmOp ops[4] = {make_op2(Mo, M, N, Dop, bf ? pl(c->HC_p) : dn(w.HC, N), c->H1, M),
+                     make_op2(Mo, M, N, Dop, bf ? pl(c->SC_p) : dn(w.SC, N), c->S1, M),
+                     make_op2(Mo, M, N, Dop, bf ? pl(c->HD_p) : dn(w.HD, N), c->H2, M),
+                     make_op2(Mo, M, N, Dop, bf ? pl(SD_p) : dn(SD, N), c->S2, M)};
     // H'' = D Hs D^T and S'' = D S D^T are symmetric (Eq. 15): their upper block triangles are
-    // computed and mirrored
-    ops[2].tri = ops[3].tri = 1;
+    // computed and mirrored (square products only: not with paired rows)
+    if (Mo == M) ops[2].tri = ops[3].tri = 1;
     TRY(gemm(c, d, ops, 4, done));
+    for (double* X : {c->H1, c->S1, c->H2, c->S2}) TRY(fill_pairs(c, X, T_F64, M, M, nullptr));
   }
   TRY(prof_mark(c));
   HIPCHK(c, line_search(c->HW, c->SW, c->H1, c->S1, c->H2, c->S2, M, c->partials, c->st,
@@ -1026,15 +1056,20 @@ int resync_fp64(omm_ctx* c) {
   Work<double>& w = c->w64;
   GemmDesc d{CF64, T_F64, T_F64, T_F64, T_F64, KC, KC, 0, 1};
   const bool sid = reduced(c);
-  GemmOp ops[2] = {make_op(M, N, N, w.C, N, c->Hs, N, w.HC, N),
-                   make_op(M, N, N, w.C, N, c->S, N, w.SC, N)};
+  const int Mo = paired_rows(c) ? paired_rows(c) : M;  // rows computed by each product
+  GemmOp ops[2] = {make_op(Mo, N, N, w.C, N, c->Hs, N, w.HC, N),
+                   make_op(Mo, N, N, w.C, N, c->S, N, w.SC, N)};
   TRY(gemm(c, d, ops, sid ? 1 : 2, nullptr));
+  TRY(fill_pairs(c, w.HC, T_F64, N, N, nullptr, false));
+  if (!sid) TRY(fill_pairs(c, w.SC, T_F64, N, N, nullptr, false));
   if (sid)
     HIPCHK(c, hipMemcpyAsync(w.SC, w.C, (size_t)M * N * sizeof(double), hipMemcpyDeviceToDevice,
                              c->stream));
-  GemmOp ops2[2] = {make_op(M, M, N, w.HC, N, w.C, N, c->HW, M),
-                    make_op(M, M, N, w.SC, N, w.C, N, c->SW, M)};
+  GemmOp ops2[2] = {make_op(Mo, M, N, w.HC, N, w.C, N, c->HW, M),
+                    make_op(Mo, M, N, w.SC, N, w.C, N, c->SW, M)};
   TRY(gemm(c, d, ops2, 2, nullptr));
+  TRY(fill_pairs(c, c->HW, T_F64, M, M, nullptr, false));
+  TRY(fill_pairs(c, c->SW, T_F64, M, M, nullptr, false));
   // the BF16x3 products read HC and SC through their planes
   TRY(split_state(c, w.HC, w.SC, false));
   const int it = c->st_host->iter;

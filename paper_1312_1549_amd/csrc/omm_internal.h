@@ -126,6 +126,11 @@ hipError_t split_bf16_t(const float* src, unsigned short* hi, unsigned short* lo
                         int cols, int64_t ld, const DevState* st, hipStream_t s);
 hipError_t split_bf16_t(const double* src, unsigned short* hi, unsigned short* lo, int rows,
                         int cols, int64_t ld, const DevState* st, hipStream_t s);
+// Real embedding of a complex matrix with 2 rh rows and 2 h columns (row length ld): rows
+// rh .. 2 rh - 1 := [-X[r][h:2h], X[r][0:h]] of rows 0 .. rh - 1 (FP64 if f64, else FP32), and
+// the same for the optional bf16 planes hi/lo (row length ldp). Skipped when st->done.
+hipError_t pair_rows(void* X, bool f64, int64_t ld, unsigned short* hi, unsigned short* lo,
+                     int64_t ldp, int rh, int h, const DevState* st, hipStream_t s);
 hipError_t convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 hipError_t copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
 hipError_t validate_symmetric(const double* A, int64_t n, double rtol, int* flags, hipStream_t s);

@@ -634,6 +634,29 @@ __global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC
   }
 }
 
+// Real embedding of a complex matrix Z (rows 2 rh): row rh + r is the pair rotation of row r,
+// [-Im z, Re z] for [Re z, Im z] (each half h columns). Products whose rows follow the row pairs
+// of C are computed for the first rh rows; this fills the others, and the same rotation of the
+// optional bf16 planes (negation flips the sign bit: bf16 rounding is symmetric).
+template <typename T>
+__global__ void k_pair_rows(T* X, int64_t ld, unsigned short* hi, unsigned short* lo, int64_t ldp,
+                            int rh, int h, const DevState* st) {
+  if (st && st->done) return;
+  for (int64_t r = blockIdx.y; r < rh; r += gridDim.y)
+    for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < 2 * (int64_t)h;
+         c += (int64_t)gridDim.x * NT) {
+      const bool neg = c < h;
+      const int64_t src = neg ? c + h : c - h;
+      const T v = X[r * ld + src];
+      X[(r + rh) * ld + c] = neg ? -v : v;
+      if (hi) {
+        const unsigned short sgn = neg ? 0x8000 : 0;
+        hi[(r + rh) * ldp + c] = hi[r * ldp + src] ^ sgn;
+        lo[(r + rh) * ldp + c] = lo[r * ldp + src] ^ sgn;
+      }
+    }
+}
+
 // HW += x (H' + H'^T) + x^2 H'', SW likewise; partial sums of Tr HW, <SW, HW>, Tr SW.
 __device__ __forceinline__ void b_update_mm(double* HW, double* SW, const double* H1, const double* S1,
                             const double* H2, const double* S2, int M, double* partials,
@@ -839,6 +862,20 @@ hipError_t split_bf16_t(const double* src, unsigned short* hi, unsigned short* l
   if (ld < rows) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_split_t<double>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(NT), 0, s,
                      src, hi, lo, rows, cols, ld, st);
+  return hipGetLastError();
+}
+
+hipError_t pair_rows(void* X, bool f64, int64_t ld, unsigned short* hi, unsigned short* lo,
+                     int64_t ldp, int rh, int h, const DevState* st, hipStream_t s) {
+  if (rh <= 0 || h <= 0) return hipSuccess;
+  if (ld < 2 * (int64_t)h || (hi && (!lo || ldp < 2 * (int64_t)h))) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((2 * (int64_t)h + NT - 1) / NT), (unsigned)(rh < 65535 ? rh : 65535));
+  if (f64)
+    hipLaunchKernelGGL(k_pair_rows<double>, grid, dim3(NT), 0, s, static_cast<double*>(X), ld, hi,
+                       lo, ldp, rh, h, st);
+  else
+    hipLaunchKernelGGL(k_pair_rows<float>, grid, dim3(NT), 0, s, static_cast<float*>(X), ld, hi, lo,
+                       ldp, rh, h, st);
   return hipGetLastError();
 }
 
