@@ -141,10 +141,11 @@ def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, resync,
 
 
 def complex_bench(args, torch):
-    """Complex Hermitian problems (k-points) through OMMComplex / OMMBatchComplex: the config-5
-    lattice made periodic along x at k = 0.3 (complex N = 4096, M = 768; real embedding 8192 x
-    1536), BF16-scheme and FP64 rates and time to 1e-8 of the closed form; and a batch of four
-    config-2 k-points (FP32 grouped launches) solved to tol 1e-10."""
+    """Complex Hermitian problems (k-points) through OMMComplex / OMMBatchComplex: the 1024-atom
+    16x8x8 lattice (4 orbitals per atom) made periodic along x at k = 0.3 (complex N = 4096,
+    M = 768; real embedding 8192 x 1536), BF16-scheme and FP64 rates and time to 1e-8 of the
+    closed form; and a batch of four k-points of the 512-atom 8x8x8 lattice (complex N = 2048,
+    M = 384; FP32 grouped launches) solved to tol 1e-10."""
     from paper_1312_1549_amd import OMMBatchComplex, OMMComplex
     from synth import bloch_system, complex_start_coefficients
 
@@ -152,7 +153,7 @@ def complex_bench(args, torch):
     log(f"complex: generating c5 at k={k}")
     s = bloch_system("c5", k, 0)
     C0 = complex_start_coefficients(s.S, s.M, 1)
-    out = {"workload": f"config-5 lattice (16x8x8, a=2.5, rc=6) periodic along x, k={k}: complex "
+    out = {"workload": f"1024-atom lattice (16x8x8, a=2.5, rc=6) periodic along x, k={k}: complex "
                        f"N={s.N}, M={s.M} (real embedding {2 * s.N} x {2 * s.M})",
            "eta": s.eta, "tau": s.tau}
 
@@ -196,9 +197,9 @@ def complex_bench(args, torch):
             log(f"complex {prec}: 1e-8 after {hit} line searches")
         conv["E_ref"] = E_ref
         out["time_to_converged_1e-8"] = conv
-    # a k-point batch: four k-points of config 2 solved together
+    # a k-point batch: four k-points of the 8x8x8 lattice solved together
     ks = (0.0, 0.1, 0.2, 0.3)
-    log("complex: k-point batch, config 2 x 4")
+    log("complex: k-point batch, 8x8x8 lattice x 4 k-points")
     systems = [bloch_system("c2", kk, 0) for kk in ks]
     b = OMMBatchComplex([x.N for x in systems], [x.M for x in systems])
     for i, x in enumerate(systems):
@@ -210,7 +211,8 @@ def complex_bench(args, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     its = b.iterations()
-    out["kpoint_batch"] = {"workload": f"config 2 (complex N=2048, M=384) at k = {list(ks)}",
+    out["kpoint_batch"] = {"workload": f"512-atom lattice (8x8x8, a=2.5, rc=6) periodic along x, "
+                                       f"complex N=2048, M=384, at k = {list(ks)}",
                            "line_searches": int(its.sum()), "wall_s": wall,
                            "line_searches_per_s": float(its.sum()) / wall,
                            "precision": "fp32 products, fp64 reductions"}

@@ -288,7 +288,7 @@ def test_fused_planes_match_separate_splits(lib_ok, c2, tile, refine, monkeypatc
 def test_symmetric_projections_on_every_tile_shape(lib_ok, c2, tile, monkeypatch):
     """H'' and S'' (Eq. 15) are computed on their upper block triangle and mirrored. With square
     (128 x 128) and non-square (256 x 128, 128 x 256) macro tiles pinned, the FP64 trajectory at
-    config 2 still follows the oracle's line search for line search."""
+    2048-orbital lattice (M = 384) still follows the oracle's line search for line search."""
     s, C0, _ = c2
     monkeypatch.setenv("OMM_TILE", tile)
     _say(f"symmetric projections, fp64 c2, tile {tile}")
