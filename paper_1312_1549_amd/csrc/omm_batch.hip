@@ -285,15 +285,18 @@ int build_lists(omm_batch* b) {
   for (size_t i = 0; i < b->sys.size(); ++i) {
     BSys& s = b->sys[i];
     const int M = (int)s.M, N = (int)s.N;
+    // complex systems (real embeddings): every product follows C's row pairs and is computed
+    // for its first M / 2 rows (group_pair_rows fills the rest)
+    const int Mo = b->cplx ? M / 2 : M;
     const int* dn = &b->st[i].done;
-    b->init1.ops.push_back(gop(M, N, N, s.C, N, s.Hs, N, s.HC, N));
-    b->init1.ops.push_back(gop(M, N, N, s.C, N, s.S32, N, s.SC, N));
-    b->init2.ops.push_back(gop(M, M, N, s.HC, N, s.C, N, s.HW, M));
-    b->init2.ops.push_back(gop(M, M, N, s.SC, N, s.C, N, s.SW, M));
+    b->init1.ops.push_back(gop(Mo, N, N, s.C, N, s.Hs, N, s.HC, N));
+    b->init1.ops.push_back(gop(Mo, N, N, s.C, N, s.S32, N, s.SC, N));
+    b->init2.ops.push_back(gop(Mo, M, N, s.HC, N, s.C, N, s.HW, M));
+    b->init2.ops.push_back(gop(Mo, M, N, s.SC, N, s.C, N, s.SW, M));
     for (int k = 0; k < 2; ++k) b->init1.done.push_back(nullptr), b->init2.done.push_back(nullptr);
     for (int p = 0; p < 2; ++p) {
       float* G = p ? s.G1 : s.G0;
-      GemmOp g = gop(M, N, M, s.HW, M, s.SC, N, G, N, -4.0, s.HC, N, 8.0);
+      GemmOp g = gop(Mo, N, M, s.HW, M, s.SC, N, G, N, -4.0, s.HC, N, 8.0);
       g.nseg = 2;
       g.A[1] = s.SW; g.lda[1] = M;
       g.B[1] = s.HC; g.ldb[1] = N;
@@ -301,17 +304,17 @@ int build_lists(omm_batch* b) {
       b->grad[p].ops.push_back(g);
       b->grad[p].done.push_back(dn);
       if (s.p_kind > 0) {
-        b->pg[p].ops.push_back(gop(M, N, N, G, N, s.P, N, s.PG, N));
+        b->pg[p].ops.push_back(gop(Mo, N, N, G, N, s.P, N, s.PG, N));
         b->pg[p].done.push_back(dn);
       }
     }
-    b->hdsd.ops.push_back(gop(M, N, N, s.D, N, s.Hs, N, s.HD, N));
-    b->hdsd.ops.push_back(gop(M, N, N, s.D, N, s.S32, N, s.SD, N));
+    b->hdsd.ops.push_back(gop(Mo, N, N, s.D, N, s.Hs, N, s.HD, N));
+    b->hdsd.ops.push_back(gop(Mo, N, N, s.D, N, s.S32, N, s.SD, N));
     for (int k = 0; k < 2; ++k) b->hdsd.done.push_back(dn);
-    b->proj.ops.push_back(gop(M, M, N, s.D, N, s.HC, N, s.H1, M));
-    b->proj.ops.push_back(gop(M, M, N, s.D, N, s.SC, N, s.S1, M));
-    b->proj.ops.push_back(gop(M, M, N, s.D, N, s.HD, N, s.H2, M));
-    b->proj.ops.push_back(gop(M, M, N, s.D, N, s.SD, N, s.S2, M));
+    b->proj.ops.push_back(gop(Mo, M, N, s.D, N, s.HC, N, s.H1, M));
+    b->proj.ops.push_back(gop(Mo, M, N, s.D, N, s.SC, N, s.S1, M));
+    b->proj.ops.push_back(gop(Mo, M, N, s.D, N, s.HD, N, s.H2, M));
+    b->proj.ops.push_back(gop(Mo, M, N, s.D, N, s.SD, N, s.S2, M));
     for (int k = 0; k < 4; ++k) b->proj.done.push_back(dn);
   }
   for (OpList* L : {&b->init1, &b->init2, &b->grad[0], &b->grad[1], &b->pg[0], &b->pg[1],
@@ -320,15 +323,33 @@ int build_lists(omm_batch* b) {
   return OMM_OK;
 }
 
+// Complex batches: the second half of the rows of the products named by `which` (see
+// group_pair_rows).
+int fill_pairs(omm_batch* b, int which, int parity, bool check_done) {
+  if (!b->cplx) return OMM_OK;
+  int mm = 0, mn = 0;
+  for (const BSys& s : b->sys) {
+    mm = std::max(mm, (int)s.M);
+    mn = std::max(mn, (int)s.N);
+  }
+  BHIP(b, group_pair_rows(b->d_sys, (int)b->sys.size(), which, parity, check_done, mm, mn,
+                          b->stream));
+  return OMM_OK;
+}
+
 // One line search of every live system (k = line-search index: parity of G, first flag).
 int batch_iteration(omm_batch* b, int k) {
   const int n = (int)b->sys.size();
   const int p = k & 1;
   BTRY(launch_list(b, b->grad[p]));
+  BTRY(fill_pairs(b, 2, p, true));
   BTRY(launch_list(b, b->pg[p]));
+  BTRY(fill_pairs(b, 3, p, true));
   BHIP(b, group_direction(b->d_sys, n, p, k == 0 ? 1 : 0, b->stream));
   BTRY(launch_list(b, b->hdsd));
+  BTRY(fill_pairs(b, 4, p, true));
   BTRY(launch_list(b, b->proj));
+  BTRY(fill_pairs(b, 5, p, true));
   BHIP(b, group_line_search(b->d_sys, n, b->stream));
   BHIP(b, group_update(b->d_sys, n, b->stream));
   return OMM_OK;
@@ -449,7 +470,7 @@ int omm_batch_minimize(omm_batch* b, const double* const* C0, const double* eta,
     s.have_C = true;
     sd[i] = SysDev{s.C, s.HC, s.SC, s.G0, s.G1, s.PG, s.D, s.HD, s.SD, s.HW, s.SW, s.H1, s.S1,
                    s.H2, s.S2, s.partials, b->st + i, s.trace, (int)s.M, (int)s.N,
-                   s.p_kind > 0 ? 1 : 0};
+                   s.p_kind > 0 ? 1 : 0, b->cplx ? 1 : 0};
     DevState& h = b->st_host[i];
     h = DevState{};
     h.tol = tol;
@@ -463,8 +484,10 @@ int omm_batch_minimize(omm_batch* b, const double* const* C0, const double* eta,
   // initial products and E_0 of every system
   BTRY(tune_list(b, b->init1));
   BTRY(launch_list(b, b->init1));
+  BTRY(fill_pairs(b, 0, 0, false));
   BTRY(tune_list(b, b->init2));
   BTRY(launch_list(b, b->init2));
+  BTRY(fill_pairs(b, 1, 0, false));
   BHIP(b, group_energy_init(b->d_sys, n, b->stream));
   BTRY(read_states(b));
   bool all_done = true;
@@ -478,12 +501,16 @@ int omm_batch_minimize(omm_batch* b, const double* const* C0, const double* eta,
     BTRY(upload_list(b, b->grad[1], b->grad[0].d.tile));
     BTRY(upload_list(b, b->pg[1], b->pg[0].d.tile));
     BTRY(launch_list(b, b->grad[0]));
+    BTRY(fill_pairs(b, 2, 0, true));
     BTRY(launch_list(b, b->pg[0]));
+    BTRY(fill_pairs(b, 3, 0, true));
     BHIP(b, group_direction(b->d_sys, n, 0, 1, b->stream));
     BTRY(tune_list(b, b->hdsd));
     BTRY(launch_list(b, b->hdsd));
+    BTRY(fill_pairs(b, 4, 0, true));
     BTRY(tune_list(b, b->proj));
     BTRY(launch_list(b, b->proj));
+    BTRY(fill_pairs(b, 5, 0, true));
     BHIP(b, group_line_search(b->d_sys, n, b->stream));
     BHIP(b, group_update(b->d_sys, n, b->stream));
     // line searches 1 and 2 (parities 1, 0) captured once, replayed until all systems stop

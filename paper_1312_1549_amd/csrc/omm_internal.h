@@ -191,6 +191,7 @@ struct SysDev {
   double* trace;                                    // max_iter + 2 entries
   int M, N;
   int precon;                                       // PG holds G P (else PG aliases G)
+  int paired;  // real embedding of a complex system: products computed for the first M / 2 rows
 };
 constexpr int GROUP_BLOCKS = 64;
 
@@ -198,6 +199,12 @@ hipError_t group_energy_init(const SysDev* d_sys, int nsys, hipStream_t s);
 hipError_t group_direction(const SysDev* d_sys, int nsys, int parity, int first, hipStream_t s);
 hipError_t group_line_search(const SysDev* d_sys, int nsys, hipStream_t s);
 hipError_t group_update(const SysDev* d_sys, int nsys, hipStream_t s);
+// Rows M/2 .. M-1 of the paired systems' products from rows 0 .. M/2-1 by the pair rotation
+// (see pair_rows): which = 0 HC, SC; 1 HW, SW; 2 G of `parity`; 3 PG; 4 HD, SD; 5 H', S', H'',
+// S''. max_m, max_n bound the systems' sizes (grid shape); stopped systems are skipped when
+// check_done.
+hipError_t group_pair_rows(const SysDev* d_sys, int nsys, int which, int parity, bool check_done,
+                           int max_m, int max_n, hipStream_t s);
 
 // ---- preconditioner (omm_precon.hip) ----
 // In-place inverse of an n x n matrix by a blocked Gauss-Jordan sweep. Returns hipSuccess and

@@ -5,6 +5,8 @@
 // no stage needs the host.
 #include <math.h>
 
+#include <algorithm>
+
 #include "omm_internal.h"
 
 namespace omm {
@@ -793,6 +795,38 @@ __global__ void g_update_mn(const SysDev* sys) {
   b_update_mn<float>(d.C, d.D, d.HC, d.HD, d.SC, d.SD, (int64_t)d.M * d.N, d.st, blockIdx.x,
                      gridDim.x);
 }
+template <typename T>
+__device__ __forceinline__ void pair_fill(T* X, int rh, int h, int64_t r, int64_t c) {
+  const bool neg = c < h;
+  const T v = X[r * 2 * h + (neg ? c + h : c - h)];
+  X[(r + rh) * 2 * h + c] = neg ? -v : v;
+}
+
+__global__ void g_pair_rows(const SysDev* sys, int which, int parity, int check_done) {
+  const SysDev& d = sys[blockIdx.z];
+  if (!d.paired || (check_done && d.st->done)) return;
+  if (which == 3 && !d.precon) return;  // PG aliases G
+  const int rh = d.M / 2;
+  const bool mm = which == 1 || which == 5;  // M x M (FP64) or M x N (FP32)
+  const int h = (mm ? d.M : d.N) / 2;
+  float* xf[2] = {nullptr, nullptr};
+  double* xd[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (which == 0) { xf[0] = d.HC; xf[1] = d.SC; }
+  if (which == 2) xf[0] = parity ? d.G1 : d.G0;
+  if (which == 3) xf[0] = d.PG;
+  if (which == 4) { xf[0] = d.HD; xf[1] = d.SD; }
+  if (which == 1) { xd[0] = d.HW; xd[1] = d.SW; }
+  if (which == 5) { xd[0] = d.H1; xd[1] = d.S1; xd[2] = d.H2; xd[3] = d.S2; }
+  for (int64_t r = blockIdx.y; r < rh; r += gridDim.y)
+    for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < 2 * (int64_t)h;
+         c += (int64_t)gridDim.x * NT) {
+      for (int a = 0; a < 2; ++a)
+        if (xf[a]) pair_fill(xf[a], rh, h, r, c);
+      for (int a = 0; a < 4; ++a)
+        if (xd[a]) pair_fill(xd[a], rh, h, r, c);
+    }
+}
+
 __global__ void g_update_mm(const SysDev* sys) {
   const SysDev& d = sys[blockIdx.y];
   b_update_mm(d.HW, d.SW, d.H1, d.S1, d.H2, d.S2, d.M, d.partials, d.st, blockIdx.x, gridDim.x);
@@ -1027,6 +1061,16 @@ hipError_t group_update(const SysDev* d_sys, int nsys, hipStream_t s) {
   hipLaunchKernelGGL(g_update_mn, dim3(4 * GROUP_BLOCKS, nsys), dim3(NT), 0, s, d_sys);
   hipLaunchKernelGGL(g_update_mm, dim3(GROUP_BLOCKS, nsys), dim3(NT), 0, s, d_sys);
   hipLaunchKernelGGL(g_update_final, dim3(1, nsys), dim3(NT), 0, s, d_sys);
+  return hipGetLastError();
+}
+
+hipError_t group_pair_rows(const SysDev* d_sys, int nsys, int which, int parity, bool check_done,
+                           int max_m, int max_n, hipStream_t s) {
+  if (nsys <= 0 || max_m < 2) return hipSuccess;
+  const int cols = (which == 1 || which == 5) ? max_m : max_n;
+  const dim3 grid((unsigned)((cols + NT - 1) / NT), (unsigned)std::min(max_m / 2, 4096),
+                  (unsigned)nsys);
+  hipLaunchKernelGGL(g_pair_rows, grid, dim3(NT), 0, s, d_sys, which, parity, check_done ? 1 : 0);
   return hipGetLastError();
 }
 

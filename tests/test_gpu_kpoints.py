@@ -57,6 +57,11 @@ def test_kpoint_batch_matches_closed_forms_and_single_runs(lib):
         single.set_HS(x.H, x.S, x.T)
         single.minimize(C0s[i], eta=0.5, tau=10.0, tol=1e-11, max_iter=5000)
         assert abs(single.energy() - E[i]) <= 1e-6 * abs(E[i]), (KS[i], single.energy(), E[i])
+        # the iterates keep the pair structure of the embedding exactly (half-row products)
+        Cr = b.get_C(i)
+        Mc, Nc = x.M, x.N
+        pair = np.concatenate([-Cr[:Mc, Nc:], Cr[:Mc, :Nc]], axis=1)
+        assert np.array_equal(Cr[Mc:], pair)
         # the returned Wannier functions are S(k)-orthonormal at the minimum (to FP32 products)
         C = b.get_C_complex(i)
         SW = (C @ x.S) @ C.conj().T
