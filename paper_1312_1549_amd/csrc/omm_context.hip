@@ -34,10 +34,11 @@ template <typename T>
 struct Work {
   T *C = nullptr, *HC = nullptr, *SC = nullptr, *G = nullptr, *Gp = nullptr, *PG = nullptr,
     *D = nullptr, *HD = nullptr, *SD = nullptr;
-  // BF16 scheme with an FP64 state: PG, HD and SD held in FP32. Their products accumulate in
-  // FP32, so the FP32 value is the product itself (the stream-K fix-up sums parts in FP64 and
-  // rounds once); the state C, HC, SC, G, D stays FP64.
-  float *PGf = nullptr, *HDf = nullptr, *SDf = nullptr;
+  // BF16 scheme with an FP64 state: G (both parities), PG, HD and SD held in FP32. Their
+  // products accumulate in FP32, so the FP32 value is the product itself (the stream-K fix-up
+  // sums parts in FP64 and rounds once; G = 8 HC - 4 (...) is formed in FP64 and rounded once);
+  // the state C, HC, SC stays FP64 and D is exact in its bf16 plane.
+  float *PGf = nullptr, *HDf = nullptr, *SDf = nullptr, *Gf = nullptr, *Gpf = nullptr;
 };
 
 // A bf16 hi/lo pair of planes (x = hi + lo) feeding the BF16x3 GEMMs.
@@ -194,6 +195,8 @@ int alloc_work(omm_ctx* c, Work<T>& w) {
     TRY(dalloc(c, &w.PGf, mn));
     TRY(dalloc(c, &w.HDf, mn));
     TRY(dalloc(c, &w.SDf, mn));
+    TRY(dalloc(c, &w.Gf, mn));
+    TRY(dalloc(c, &w.Gpf, mn));
   }
   return OMM_OK;
 }
@@ -202,7 +205,7 @@ template <typename T>
 void free_work(Work<T>& w) {
   dfree(w.C); dfree(w.HC); dfree(w.SC); dfree(w.G); dfree(w.Gp); dfree(w.PG); dfree(w.D);
   dfree(w.HD); dfree(w.SD);
-  dfree(w.PGf); dfree(w.HDf); dfree(w.SDf);
+  dfree(w.PGf); dfree(w.HDf); dfree(w.SDf); dfree(w.Gf); dfree(w.Gpf);
 }
 
 // Row length of a bf16 plane with `cols` columns: a multiple of 64 elements, so that every row
@@ -797,8 +800,14 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   const int et = elem_type<T>();
   const int ot = bf ? T_BF16P : et;  // operand element type of the GEMMs
   const int* done = &c->st->done;
+  // BF16 with the FP64 state: the products G, PG, HD, SD are stored in FP32 (see Work)
+  const bool f32p = bf && sizeof(T) == 8 && w.PGf != nullptr;
   T* G = (k & 1) ? w.Gp : w.G;
   T* Gprev = (k & 1) ? w.G : w.Gp;
+  float* Gf = (k & 1) ? w.Gpf : w.Gf;
+  float* Gfprev = (k & 1) ? w.Gf : w.Gpf;
+  void* Gout = f32p ? (void*)Gf : (void*)G;
+  const int tg = f32p ? T_F32 : et;
   TRY(prof_mark(c));
   // G = 8 HC - 4 HW SC - 4 SW HC
   {
@@ -807,9 +816,9 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
       TRY(split(c, c->SW, c->SW_p, M, M));
     }
     // BF16x3 reads the transposed planes of SC, HC (k-contiguous); the others read SC, HC by rows
-    GemmDesc d{compute, bf ? T_BF16P : T_F64, ot, et, et, KC, bf ? KC : RC, 0, 1};
+    GemmDesc d{compute, bf ? T_BF16P : T_F64, ot, tg, et, KC, bf ? KC : RC, 0, 1};
     GemmOp op = make_op2(Mo, N, M, bf ? pl(c->HW_p) : dn(c->HW, M),
-                         bf ? pl(c->SCt_p) : dn(w.SC, N), G, N, -4.0, w.HC, N, 8.0);
+                         bf ? pl(c->SCt_p) : dn(w.SC, N), Gout, N, -4.0, w.HC, N, 8.0);
     const Opnd a2 = bf ? pl(c->SW_p) : dn(c->SW, M), b2 = bf ? pl(c->HCt_p) : dn(w.HC, N);
     op.nseg = 2;
     op.A[1] = a2.p; op.Alo[1] = a2.lo; op.lda[1] = a2.ld;
@@ -818,7 +827,7 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     // G's planes for the preconditioner product, from the epilogue
     if (fuse && c->p_kind > 0) out_planes(op, c->G_p);
     TRY(gemm(c, d, &op, 1, done));
-    TRY(fill_pairs(c, G, et, N, N, fuse && c->p_kind > 0 ? &c->G_p : nullptr));
+    TRY(fill_pairs(c, Gout, tg, N, N, fuse && c->p_kind > 0 ? &c->G_p : nullptr));
   }
   TRY(prof_mark(c));
   // BF16x3: the preconditioner is applied as its bf16 rounding (the hi plane of P, a symmetric
@@ -827,10 +836,11 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
   // operand is exact).
   const int cP = bf ? CBF16X2B : compute, cD = bf ? CBF16X2A : compute;
   T* PG = G;
-  // BF16 with the FP64 state: the products PG, HD, SD are stored in FP32 (see Work)
-  const bool f32p = bf && sizeof(T) == 8 && w.PGf != nullptr;
   if (c->p_kind > 0) {
-    if (bf && !fuse) TRY(split(c, G, c->G_p, M, N));
+    if (bf && !fuse) {
+      if (f32p) TRY(split(c, Gf, c->G_p, M, N));
+      else TRY(split(c, G, c->G_p, M, N));
+    }
     const int tp = f32p ? T_F32 : et;
     GemmDesc d{cP, ot, ot, tp, tp, KC, KC, 0, 1};
     GemmOp op = make_op2(Mo, N, N, bf ? pl(c->G_p) : dn(G, N), bf ? pl(c->P_p) : dn(P, N),
@@ -840,11 +850,19 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     PG = w.PG;
   }
   TRY(prof_mark(c));
+  // BF16: D lives in its bf16 plane (exact); the fused update reads it there, so the T copy is
+  // written only for the separate update
+  T* Dcopy = fuse ? nullptr : w.D;
   if (f32p && c->p_kind > 0)
-    HIPCHK(c, (beta_and_direction<T, float>(G, w.PGf, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials,
-                                           c->st, c->stream, c->D_p.hi, N, c->D_p.ld)));
+    HIPCHK(c, (beta_and_direction<T, float, float>(Gf, w.PGf, Gfprev, Dcopy, mn, k == 0 ? 1 : 0,
+                                                  c->partials, c->st, c->stream, c->D_p.hi, N,
+                                                  c->D_p.ld)));
+  else if (f32p)  // no preconditioner: PG = G
+    HIPCHK(c, (beta_and_direction<T, float, float>(Gf, Gf, Gfprev, Dcopy, mn, k == 0 ? 1 : 0,
+                                                  c->partials, c->st, c->stream, c->D_p.hi, N,
+                                                  c->D_p.ld)));
   else
-    HIPCHK(c, beta_and_direction<T>(G, PG, Gprev, w.D, mn, k == 0 ? 1 : 0, c->partials, c->st,
+    HIPCHK(c, beta_and_direction<T>(G, PG, Gprev, Dcopy, mn, k == 0 ? 1 : 0, c->partials, c->st,
                                     c->stream, bf ? c->D_p.hi : nullptr, N, c->D_p.ld));
   TRY(prof_mark(c));
   const Opnd Dop = bf ? pl(c->D_p) : dn(w.D, N);
@@ -905,11 +923,11 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
                          c->HCt_p.hi, c->HCt_p.lo, c->SCt_p.hi, c->SCt_p.lo,
                          c->HC_p.ld,  c->HCt_p.ld};
     if (hdf)
-      HIPCHK(c, (update_coefficients_split<T, float>(w.C, w.D, w.HC, w.HDf, w.SC, w.SDf, M, N, sp,
-                                                    c->st, c->stream)));
+      HIPCHK(c, (update_coefficients_split<T, float>(w.C, c->D_p.hi, c->D_p.ld, w.HC, w.HDf, w.SC,
+                                                    w.SDf, M, N, sp, c->st, c->stream)));
     else
-      HIPCHK(c, update_coefficients_split<T>(w.C, w.D, w.HC, w.HD, w.SC, SD, M, N, sp, c->st,
-                                             c->stream));
+      HIPCHK(c, update_coefficients_split<T>(w.C, c->D_p.hi, c->D_p.ld, w.HC, w.HD, w.SC,
+                                             sid ? nullptr : w.SD, M, N, sp, c->st, c->stream));
   } else {
     if (hdf)
       HIPCHK(c, (update_coefficients<T, float>(w.C, w.D, w.HC, w.HDf, w.SC, w.SDf, mn, c->st,

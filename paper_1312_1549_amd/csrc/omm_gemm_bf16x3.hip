@@ -19,6 +19,10 @@ gemm_fn pick_bf16x3(const GemmDesc& d) {
     return pick2<P, P, float, float>(d);
   if (d.ta == T_BF16P && d.tb == T_BF16P && d.tc == T_F64 && d.tx == T_F64)
     return pick2<P, P, double, double>(d);
+  // FP32 output with an FP64 addend (the gradient over the FP64 state)
+  if (d.ta == T_BF16P && d.tb == T_BF16P && d.tc == T_F32 && d.tx == T_F64 && d.la == KC &&
+      d.lb == KC)
+    return pick_tile<CBF16X3, P, P, float, double, KC, KC>(d.tile);
   return nullptr;
 }
 

@@ -587,7 +587,7 @@ __device__ __forceinline__ void wait_vm_lgkm0() {
 }
 
 constexpr int DMA_TM = 8, DMA_TN = 4;  // 16 x 16 blocks per wave (wave grid 2 x 4)
-template <int KIND, typename TC>
+template <int KIND, typename TC, typename TX>
 struct DmaUser {
   static constexpr int kind = KIND;  // 0: one tile per workgroup, 1: stream-K
 };
@@ -786,7 +786,7 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_dma(GemmBatch batch, const
   const int per = (nk + nsplit - 1) / nsplit;
   const int sp = blockIdx.y;
   f4 acc[DMA_TM][DMA_TN];
-  gemm_tile_dma_acc<MODE, NS, DmaUser<0, TC>>(op, tm, tn, sp * per * DMA_BK,
+  gemm_tile_dma_acc<MODE, NS, DmaUser<0, TC, TX>>(op, tm, tn, sp * per * DMA_BK,
                                               min(ktot, (sp + 1) * per * DMA_BK), acc);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   store_acc<MODE, TC, TX, DMA_TM, DMA_TN>(op, acc, tm * DMA_BM + (wave % 2) * DMA_TM * 16,
@@ -860,7 +860,7 @@ __global__ __launch_bounds__(512, 1) void gemm_kernel_sk(GemmBatch batch, const 
     }
     int tm, tn;
     const GemmOp* op = sk_locate(batch, a.nops, to, tm, tn);
-    gemm_tile_dma_acc<MODE, NS, DmaUser<1, TC>>(*op, tm, tn, k0 * DMA_BK, min(ktot, k1 * DMA_BK),
+    gemm_tile_dma_acc<MODE, NS, DmaUser<1, TC, TX>>(*op, tm, tn, k0 * DMA_BK, min(ktot, k1 * DMA_BK),
                                                 acc);
     if (k0 == 0 && k1 == a.nk) {
       store_acc<MODE, TC, TX, DMA_TM, DMA_TN>(*op, acc, tm * DMA_BM + (wave % 2) * DMA_TM * 16,

@@ -140,11 +140,12 @@ hipError_t symmetrize(double* A, int64_t n, hipStream_t s);
 hipError_t energy_init(const double* HW, const double* SW, int M, double* partials, DevState* st,
                        double* trace, hipStream_t s);
 
-// Polak-Ribiere beta and D = -PG + beta D. With `hi` non-null D is rounded to bf16 in place and
-// its bits are written to `hi` (the single-plane operand of the two-product GEMMs): D is then
-// (n / cols) x cols and hi has rows of length ld.
-template <typename T, typename TP = T>
-hipError_t beta_and_direction(const T* G, const TP* PG, const T* Gprev, T* D, int64_t n, int first,
+// Polak-Ribiere beta and D = -PG + beta D. With `hi` non-null D is rounded to bf16 and its bits
+// are written to `hi` (the single-plane operand of the two-product GEMMs; rows of length ld,
+// n / cols of them); the previous direction is then read back from `hi`, and D, which may be
+// null, only receives a copy of the rounded values.
+template <typename T, typename TP = T, typename TG = T>
+hipError_t beta_and_direction(const TG* G, const TP* PG, const TG* Gprev, T* D, int64_t n, int first,
                               double* partials, DevState* st, hipStream_t s,
                               unsigned short* hi = nullptr, int64_t cols = 0, int64_t ld = 0);
 
@@ -166,11 +167,13 @@ struct StatePlanes {
   int64_t ld, ldt;
 };
 // update_coefficients (rows x cols arrays) fused with the splits of the new HC and SC into `p`
-// (the same values split_bf16 and split_bf16_t would write).
+// (the same values split_bf16 and split_bf16_t would write). The direction is read from its bf16
+// plane Dh (rows of length ldd; D is exact in bf16 in this scheme); SD null means SD = D (the
+// reduced problem, S~ = I).
 template <typename T, typename TD = T>
-hipError_t update_coefficients_split(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD,
-                                     int rows, int cols, const StatePlanes& p, const DevState* st,
-                                     hipStream_t s);
+hipError_t update_coefficients_split(T* C, const unsigned short* Dh, int64_t ldd, T* HC,
+                                     const TD* HD, T* SC, const TD* SD, int rows, int cols,
+                                     const StatePlanes& p, const DevState* st, hipStream_t s);
 
 hipError_t update_subspace(double* HW, double* SW, const double* H1, const double* S1,
                            const double* H2, const double* S2, int M, double* partials,

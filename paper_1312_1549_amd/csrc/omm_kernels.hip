@@ -306,11 +306,14 @@ __global__ void k_direction_bf16(const TP* PG, T* D, unsigned short* hi, int64_t
   for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
     for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < cols;
          c += (int64_t)gridDim.x * NT) {
-      const int64_t i = r * cols + c;
-      const double d = first ? -(double)PG[i] : -(double)PG[i] + beta * (double)D[i];
+      const int64_t i = r * cols + c, q = r * ld + c;
+      // the previous direction is exact in bf16: read back from its plane
+      const double d =
+          first ? -(double)PG[i]
+                : -(double)PG[i] + beta * (double)__uint_as_float(((unsigned int)hi[q]) << 16);
       const unsigned short hb = bf16_bits((float)d);
-      hi[r * ld + c] = hb;
-      D[i] = (T)__uint_as_float(((unsigned int)hb) << 16);
+      hi[q] = hb;
+      if (D) D[i] = (T)__uint_as_float(((unsigned int)hb) << 16);
     }
 }
 
@@ -502,9 +505,14 @@ __device__ __forceinline__ void split_store(double v, unsigned short* hi, unsign
 
 // Eq. 16 for C, HC, SC (rows x cols) with the bf16 planes of the new HC and SC, row-major and
 // transposed (through a 32 x 33 LDS tile), one 32 x 32 tile per block.
+__device__ __forceinline__ float bf16_value(unsigned short b) {
+  return __uint_as_float(((unsigned int)b) << 16);
+}
+
 template <typename T, typename TD>
-__global__ void k_update_split_mn(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD,
-                                  int rows, int cols, StatePlanes p, const DevState* st) {
+__global__ void k_update_split_mn(T* C, const unsigned short* Dh, int64_t ldd, T* HC, const TD* HD,
+                                  T* SC, const TD* SD, int rows, int cols, StatePlanes p,
+                                  const DevState* st) {
   if (st->done) return;
   __shared__ T th[32][33], ts[32][33];
   const double x = st->x;
@@ -515,9 +523,10 @@ __global__ void k_update_split_mn(T* C, const T* D, T* HC, const TD* HD, T* SC, 
     T h = (T)0, v = (T)0;
     if (gr < rows && gc < cols) {
       const int64_t e = (int64_t)gr * cols + gc;
-      C[e] = (T)((double)C[e] + x * (double)D[e]);
+      const double d = (double)bf16_value(Dh[(int64_t)gr * ldd + gc]);
+      C[e] = (T)((double)C[e] + x * d);
       h = (T)((double)HC[e] + x * (double)HD[e]);
-      v = (T)((double)SC[e] + x * (double)SD[e]);
+      v = (T)((double)SC[e] + x * (SD ? (double)SD[e] : d));
       HC[e] = h;
       SC[e] = v;
       const int64_t q = (int64_t)gr * p.ld + gc;
@@ -549,8 +558,9 @@ __device__ __forceinline__ unsigned split_word(double v) {
 }
 
 template <typename T, typename TD>
-__global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC, const TD* HD,
-                                                         T* SC, const TD* SD, int rows, int cols,
+__global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const unsigned short* Dh,
+                                                         int64_t ldd, T* HC, const TD* HD, T* SC,
+                                                         const TD* SD, int rows, int cols,
                                                          StatePlanes p, const DevState* st) {
   if (st->done) return;
   typedef T T2 __attribute__((ext_vector_type(2)));
@@ -564,8 +574,9 @@ __global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC
   constexpr int RB = 4;
 #pragma unroll
   for (int b = 0; b < 8; b += RB) {
-    T2 c[RB], d[RB], hc[RB], sc[RB];
+    T2 c[RB], hc[RB], sc[RB];
     TD2 hd[RB], sd[RB];
+    unsigned dw[RB];  // two bf16 directions
     bool in[RB];
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
@@ -574,11 +585,11 @@ __global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC
       if (in[k]) {
         const int64_t e = (int64_t)gr * cols + gc;
         c[k] = *reinterpret_cast<const T2*>(C + e);
-        d[k] = *reinterpret_cast<const T2*>(D + e);
+        dw[k] = *reinterpret_cast<const unsigned*>(Dh + (int64_t)gr * ldd + gc);
         hc[k] = *reinterpret_cast<const T2*>(HC + e);
         hd[k] = *reinterpret_cast<const TD2*>(HD + e);
         sc[k] = *reinterpret_cast<const T2*>(SC + e);
-        sd[k] = *reinterpret_cast<const TD2*>(SD + e);
+        if (SD) sd[k] = *reinterpret_cast<const TD2*>(SD + e);
       }
     }
 #pragma unroll
@@ -587,13 +598,15 @@ __global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const T* D, T* HC
       unsigned wh0 = 0, wh1 = 0, ws0 = 0, ws1 = 0;
       if (in[k]) {
         const int64_t e = (int64_t)gr * cols + gc;
+        const double d0 = (double)__uint_as_float(dw[k] << 16);
+        const double d1 = (double)__uint_as_float(dw[k] & 0xffff0000u);
         T2 cn, h, v;
-        cn.x = (T)((double)c[k].x + x * (double)d[k].x);
-        cn.y = (T)((double)c[k].y + x * (double)d[k].y);
+        cn.x = (T)((double)c[k].x + x * d0);
+        cn.y = (T)((double)c[k].y + x * d1);
         h.x = (T)((double)hc[k].x + x * (double)hd[k].x);
         h.y = (T)((double)hc[k].y + x * (double)hd[k].y);
-        v.x = (T)((double)sc[k].x + x * (double)sd[k].x);
-        v.y = (T)((double)sc[k].y + x * (double)sd[k].y);
+        v.x = (T)((double)sc[k].x + x * (SD ? (double)sd[k].x : d0));
+        v.y = (T)((double)sc[k].y + x * (SD ? (double)sd[k].y : d1));
         *reinterpret_cast<T2*>(C + e) = cn;
         *reinterpret_cast<T2*>(HC + e) = h;
         *reinterpret_cast<T2*>(SC + e) = v;
@@ -950,12 +963,13 @@ hipError_t block_pattern(const double* B, int64_t n, unsigned char* flags, hipSt
   return hipGetLastError();
 }
 
-template <typename T, typename TP>
-hipError_t beta_and_direction(const T* G, const TP* PG, const T* Gprev, T* D, int64_t n, int first,
+template <typename T, typename TP, typename TG>
+hipError_t beta_and_direction(const TG* G, const TP* PG, const TG* Gprev, T* D, int64_t n, int first,
                               double* partials, DevState* st, hipStream_t s, unsigned short* hi,
                               int64_t cols, int64_t ld) {
+  if (!hi && !D) return hipErrorInvalidValue;
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL((k_pr_partials<T, TP>), dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first,
+  hipLaunchKernelGGL((k_pr_partials<TG, TP>), dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first,
                      partials, st);
   hipLaunchKernelGGL(k_pr_final, dim3(1), dim3(NT), 0, s, partials, nb, first, st);
   if (hi) {
@@ -968,13 +982,14 @@ hipError_t beta_and_direction(const T* G, const TP* PG, const T* Gprev, T* D, in
   }
   return hipGetLastError();
 }
-#define OMM_BETA_DIRECTION(T, TP)                                                                \
-  template hipError_t beta_and_direction<T, TP>(const T*, const TP*, const T*, T*, int64_t, int,  \
-                                                double*, DevState*, hipStream_t, unsigned short*, \
-                                                int64_t, int64_t);
-OMM_BETA_DIRECTION(double, double)
-OMM_BETA_DIRECTION(float, float)
-OMM_BETA_DIRECTION(double, float)
+#define OMM_BETA_DIRECTION(T, TP, TG)                                                            \
+  template hipError_t beta_and_direction<T, TP, TG>(const TG*, const TP*, const TG*, T*, int64_t, \
+                                                    int, double*, DevState*, hipStream_t,         \
+                                                    unsigned short*, int64_t, int64_t);
+OMM_BETA_DIRECTION(double, double, double)
+OMM_BETA_DIRECTION(float, float, float)
+OMM_BETA_DIRECTION(double, float, double)
+OMM_BETA_DIRECTION(double, float, float)
 #undef OMM_BETA_DIRECTION
 
 hipError_t line_search(const double* HW, const double* SW, const double* H1, const double* S1,
@@ -1003,26 +1018,28 @@ OMM_UPDATE(double, float)
 #undef OMM_UPDATE
 
 template <typename T, typename TD>
-hipError_t update_coefficients_split(T* C, const T* D, T* HC, const TD* HD, T* SC, const TD* SD,
-                                     int rows, int cols, const StatePlanes& p, const DevState* st,
-                                     hipStream_t s) {
+hipError_t update_coefficients_split(T* C, const unsigned short* Dh, int64_t ldd, T* HC,
+                                     const TD* HD, T* SC, const TD* SD, int rows, int cols,
+                                     const StatePlanes& p, const DevState* st, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  if (p.ld < cols || p.ldt < rows) return hipErrorInvalidValue;
-  const bool wide = cols % 2 == 0 && p.ld % 2 == 0 && p.ldt % 2 == 0 &&
-                    ((uintptr_t)C | (uintptr_t)D | (uintptr_t)HC | (uintptr_t)SC) % (2 * sizeof(T)) == 0 &&
+  if (!Dh || ldd < cols || p.ld < cols || p.ldt < rows) return hipErrorInvalidValue;
+  const bool wide = cols % 2 == 0 && p.ld % 2 == 0 && p.ldt % 2 == 0 && ldd % 2 == 0 &&
+                    (uintptr_t)Dh % 4 == 0 &&
+                    ((uintptr_t)C | (uintptr_t)HC | (uintptr_t)SC) % (2 * sizeof(T)) == 0 &&
                     ((uintptr_t)HD | (uintptr_t)SD) % (2 * sizeof(TD)) == 0;
   if (wide)
     hipLaunchKernelGGL((k_update_split_mn2<T, TD>), dim3((cols + 63) / 64, (rows + 63) / 64),
-                       dim3(NT), 0, s, C, D, HC, HD, SC, SD, rows, cols, p, st);
+                       dim3(NT), 0, s, C, Dh, ldd, HC, HD, SC, SD, rows, cols, p, st);
   else
     hipLaunchKernelGGL((k_update_split_mn<T, TD>), dim3((cols + 31) / 32, (rows + 31) / 32),
-                       dim3(NT), 0, s, C, D, HC, HD, SC, SD, rows, cols, p, st);
+                       dim3(NT), 0, s, C, Dh, ldd, HC, HD, SC, SD, rows, cols, p, st);
   return hipGetLastError();
 }
 #define OMM_UPDATE_SPLIT(T, TD)                                                                  \
-  template hipError_t update_coefficients_split<T, TD>(T*, const T*, T*, const TD*, T*,          \
-                                                       const TD*, int, int, const StatePlanes&,  \
-                                                       const DevState*, hipStream_t);
+  template hipError_t update_coefficients_split<T, TD>(T*, const unsigned short*, int64_t, T*,   \
+                                                       const TD*, T*, const TD*, int, int,       \
+                                                       const StatePlanes&, const DevState*,      \
+                                                       hipStream_t);
 OMM_UPDATE_SPLIT(double, double)
 OMM_UPDATE_SPLIT(float, float)
 OMM_UPDATE_SPLIT(double, float)
