@@ -246,6 +246,54 @@ __global__ void k_pr_partials(const T* G, const TP* PG, const T* Gp, int64_t n, 
   b_pr_partials(G, PG, Gp, n, first, partials, st, blockIdx.x, gridDim.x);
 }
 
+// The same sums four elements per load (arrays 4-element aligned; the tail past the last full
+// group of four is added by block 0), two groups in flight per thread.
+template <typename TG, typename TP>
+__global__ void k_pr_partials4(const TG* G, const TP* PG, const TG* Gp, int64_t n, int first,
+                               double* partials, const DevState* st) {
+  if (st->done) return;
+  typedef TG G4 __attribute__((ext_vector_type(4)));
+  typedef TP P4 __attribute__((ext_vector_type(4)));
+  __shared__ double sh[NT / 64];
+  const int64_t n4 = n / 4, stride = (int64_t)gridDim.x * NT;
+  const G4* g4 = reinterpret_cast<const G4*>(G);
+  const G4* q4 = reinterpret_cast<const G4*>(Gp);
+  const P4* p4 = reinterpret_cast<const P4*>(PG);
+  double s1 = 0.0, s2 = 0.0;
+  int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  for (; i + stride < n4; i += 2 * stride) {
+    const P4 pa = p4[i], pb = p4[i + stride];
+    const G4 ga = g4[i], gb = g4[i + stride];
+    s1 += (double)pa.x * ga.x + (double)pa.y * ga.y + (double)pa.z * ga.z + (double)pa.w * ga.w;
+    s1 += (double)pb.x * gb.x + (double)pb.y * gb.y + (double)pb.z * gb.z + (double)pb.w * gb.w;
+    if (!first) {
+      const G4 qa = q4[i], qb = q4[i + stride];
+      s2 += (double)pa.x * qa.x + (double)pa.y * qa.y + (double)pa.z * qa.z + (double)pa.w * qa.w;
+      s2 += (double)pb.x * qb.x + (double)pb.y * qb.y + (double)pb.z * qb.z + (double)pb.w * qb.w;
+    }
+  }
+  if (i < n4) {
+    const P4 pa = p4[i];
+    const G4 ga = g4[i];
+    s1 += (double)pa.x * ga.x + (double)pa.y * ga.y + (double)pa.z * ga.z + (double)pa.w * ga.w;
+    if (!first) {
+      const G4 qa = q4[i];
+      s2 += (double)pa.x * qa.x + (double)pa.y * qa.y + (double)pa.z * qa.z + (double)pa.w * qa.w;
+    }
+  }
+  if (blockIdx.x == 0)
+    for (int64_t j = 4 * n4 + threadIdx.x; j < n; j += NT) {
+      s1 += (double)PG[j] * (double)G[j];
+      if (!first) s2 += (double)PG[j] * (double)Gp[j];
+    }
+  double a = block_sum(s1, sh);
+  double b = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 2 + 0] = a;
+    partials[blockIdx.x * 2 + 1] = b;
+  }
+}
+
 __device__ __forceinline__ void f_pr_final(const double* partials, int nb, int first, DevState* st) {
   if (st->done) return;
   __shared__ double sh[NT / 64];
@@ -315,6 +363,49 @@ __global__ void k_direction_bf16(const TP* PG, T* D, unsigned short* hi, int64_t
       hi[q] = hb;
       if (D) D[i] = (T)__uint_as_float(((unsigned int)hb) << 16);
     }
+}
+
+// The same, four columns per thread (cols and ld multiples of 4, aligned rows) and four rows per
+// block, all loads of a block's rows issued before its stores.
+template <typename T, typename TP>
+__global__ void k_direction_bf16x4(const TP* PG, T* D, unsigned short* hi, int64_t rows,
+                                   int64_t cols, int64_t ld, int first, const DevState* st) {
+  if (st->done) return;
+  typedef TP P4 __attribute__((ext_vector_type(4)));
+  typedef unsigned short U4 __attribute__((ext_vector_type(4)));
+  constexpr int RB = 4;
+  const double beta = st->beta;
+  const int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (4 * c >= cols) return;
+  for (int64_t r0 = (int64_t)blockIdx.y * RB; r0 < rows; r0 += (int64_t)gridDim.y * RB) {
+    P4 pg[RB];
+    U4 hv[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int64_t r = r0 + k;
+      if (r < rows) {
+        pg[k] = *reinterpret_cast<const P4*>(PG + r * cols + 4 * c);
+        if (!first) hv[k] = *reinterpret_cast<const U4*>(hi + r * ld + 4 * c);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int64_t r = r0 + k;
+      if (r >= rows) continue;
+      U4 h;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double prev = first ? 0.0 : (double)__uint_as_float(((unsigned int)hv[k][e]) << 16);
+        const double d = first ? -(double)pg[k][e] : -(double)pg[k][e] + beta * prev;
+        h[e] = bf16_bits((float)d);
+      }
+      *reinterpret_cast<U4*>(hi + r * ld + 4 * c) = h;
+      if (D)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          D[r * cols + 4 * c + e] = (T)__uint_as_float(((unsigned int)h[e]) << 16);
+    }
+  }
 }
 
 // ---- quartic coefficients (Eq. 13) --------------------------------------------------------------
@@ -550,11 +641,18 @@ __global__ void k_update_split_mn(T* C, const unsigned short* Dh, int64_t ldd, T
 // The same for an even number of columns (8-byte aligned rows), one 64 x 64 tile per block:
 // each thread takes two adjacent columns, so the T arrays move in 16-byte and the planes in
 // 4-byte (two bf16) accesses, and every plane row segment a block writes (also transposed) is
-// one 128-byte line. The transpose goes through LDS as packed (hi | lo << 16) words.
+// one 128-byte line. The transpose goes through LDS as packed (hi | lo << 16) words. Every store
+// is non-temporal (see stream_store).
 __device__ __forceinline__ unsigned split_word(double v) {
   const unsigned hb = bf16_bits((float)v);
   const unsigned lb = bf16_bits((float)(v - (double)__uint_as_float(hb << 16)));
   return hb | (lb << 16);
+}
+
+// Two bf16 values as one 4-byte store that bypasses the caches' normal retention: everything
+// the update writes is next read a whole line search later, long after it would have left L2.
+__device__ __forceinline__ void stream_store(unsigned w, unsigned short* dst) {
+  __builtin_nontemporal_store(w, reinterpret_cast<unsigned*>(dst));
 }
 
 template <typename T, typename TD>
@@ -607,18 +705,18 @@ __global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const unsigned sh
         h.y = (T)((double)hc[k].y + x * (double)hd[k].y);
         v.x = (T)((double)sc[k].x + x * (SD ? (double)sd[k].x : d0));
         v.y = (T)((double)sc[k].y + x * (SD ? (double)sd[k].y : d1));
-        *reinterpret_cast<T2*>(C + e) = cn;
-        *reinterpret_cast<T2*>(HC + e) = h;
-        *reinterpret_cast<T2*>(SC + e) = v;
+        __builtin_nontemporal_store(cn, reinterpret_cast<T2*>(C + e));
+        __builtin_nontemporal_store(h, reinterpret_cast<T2*>(HC + e));
+        __builtin_nontemporal_store(v, reinterpret_cast<T2*>(SC + e));
         wh0 = split_word((double)h.x);
         wh1 = split_word((double)h.y);
         ws0 = split_word((double)v.x);
         ws1 = split_word((double)v.y);
         const int64_t q = (int64_t)gr * p.ld + gc;
-        *reinterpret_cast<unsigned*>(p.hc_hi + q) = (wh0 & 0xffffu) | (wh1 << 16);
-        *reinterpret_cast<unsigned*>(p.hc_lo + q) = (wh0 >> 16) | (wh1 & 0xffff0000u);
-        *reinterpret_cast<unsigned*>(p.sc_hi + q) = (ws0 & 0xffffu) | (ws1 << 16);
-        *reinterpret_cast<unsigned*>(p.sc_lo + q) = (ws0 >> 16) | (ws1 & 0xffff0000u);
+        stream_store((wh0 & 0xffffu) | (wh1 << 16), p.hc_hi + q);
+        stream_store((wh0 >> 16) | (wh1 & 0xffff0000u), p.hc_lo + q);
+        stream_store((ws0 & 0xffffu) | (ws1 << 16), p.sc_hi + q);
+        stream_store((ws0 >> 16) | (ws1 & 0xffff0000u), p.sc_lo + q);
       }
       th[r][2 * tx] = wh0;
       th[r][2 * tx + 1] = wh1;
@@ -636,10 +734,10 @@ __global__ __launch_bounds__(NT) void k_update_split_mn2(T* C, const unsigned sh
     const int64_t o = (int64_t)oc * p.ldt + orow;
     if (orow + 1 < rows) {
       const unsigned a1 = th[2 * tx + 1][j], b1 = ts[2 * tx + 1][j];
-      *reinterpret_cast<unsigned*>(p.hct_hi + o) = (a0 & 0xffffu) | (a1 << 16);
-      *reinterpret_cast<unsigned*>(p.hct_lo + o) = (a0 >> 16) | (a1 & 0xffff0000u);
-      *reinterpret_cast<unsigned*>(p.sct_hi + o) = (b0 & 0xffffu) | (b1 << 16);
-      *reinterpret_cast<unsigned*>(p.sct_lo + o) = (b0 >> 16) | (b1 & 0xffff0000u);
+      stream_store((a0 & 0xffffu) | (a1 << 16), p.hct_hi + o);
+      stream_store((a0 >> 16) | (a1 & 0xffff0000u), p.hct_lo + o);
+      stream_store((b0 & 0xffffu) | (b1 << 16), p.sct_hi + o);
+      stream_store((b0 >> 16) | (b1 & 0xffff0000u), p.sct_lo + o);
     } else {
       p.hct_hi[o] = (unsigned short)(a0 & 0xffffu);
       p.hct_lo[o] = (unsigned short)(a0 >> 16);
@@ -969,14 +1067,29 @@ hipError_t beta_and_direction(const TG* G, const TP* PG, const TG* Gprev, T* D, 
                               int64_t cols, int64_t ld) {
   if (!hi && !D) return hipErrorInvalidValue;
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL((k_pr_partials<TG, TP>), dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first,
-                     partials, st);
+  const bool vec = ((uintptr_t)G | (uintptr_t)Gprev) % (4 * sizeof(TG)) == 0 &&
+                   (uintptr_t)PG % (4 * sizeof(TP)) == 0;
+  if (vec)
+    hipLaunchKernelGGL((k_pr_partials4<TG, TP>), dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first,
+                       partials, st);
+  else
+    hipLaunchKernelGGL((k_pr_partials<TG, TP>), dim3(nb), dim3(NT), 0, s, G, PG, Gprev, n, first,
+                       partials, st);
   hipLaunchKernelGGL(k_pr_final, dim3(1), dim3(NT), 0, s, partials, nb, first, st);
   if (hi) {
     if (cols <= 0 || n % cols != 0 || ld < cols) return hipErrorInvalidValue;
-    const int64_t rows = n / cols, bx = (cols + NT - 1) / NT;
-    hipLaunchKernelGGL((k_direction_bf16<T, TP>), dim3((unsigned)bx, (unsigned)(rows < 65535 ? rows : 65535)),
-                       dim3(NT), 0, s, PG, D, hi, rows, cols, ld, first, st);
+    const int64_t rows = n / cols;
+    const bool vec4 = cols % 4 == 0 && ld % 4 == 0 && (uintptr_t)PG % (4 * sizeof(TP)) == 0 &&
+                      (uintptr_t)hi % 8 == 0;
+    if (vec4) {
+      const int64_t bx = (cols / 4 + NT - 1) / NT, by = (rows + 3) / 4;
+      hipLaunchKernelGGL((k_direction_bf16x4<T, TP>), dim3((unsigned)bx, (unsigned)(by < 65535 ? by : 65535)),
+                         dim3(NT), 0, s, PG, D, hi, rows, cols, ld, first, st);
+    } else {
+      const int64_t bx = (cols + NT - 1) / NT;
+      hipLaunchKernelGGL((k_direction_bf16<T, TP>), dim3((unsigned)bx, (unsigned)(rows < 65535 ? rows : 65535)),
+                         dim3(NT), 0, s, PG, D, hi, rows, cols, ld, first, st);
+    }
   } else {
     hipLaunchKernelGGL((k_direction<T, TP>), dim3(ew_blocks(n)), dim3(NT), 0, s, PG, D, n, first, st);
   }
