@@ -815,10 +815,79 @@ __device__ __forceinline__ void b_update_mm(double* HW, double* SW, const double
   }
 }
 
-__global__ void k_update_mm(double* HW, double* SW, const double* H1, const double* S1,
-                            const double* H2, const double* S2, int M, double* partials,
-                            const DevState* st) {
-  b_update_mm(HW, SW, H1, S1, H2, S2, M, partials, st, blockIdx.x, gridDim.x);
+// The same update for one system, using that HW, SW, H'' and S'' are symmetric: each block takes a
+// pair of 32 x 32 tiles (bi, bj), bi <= bj, computes the upper one from the upper tiles of HW,
+// SW, H'', S'' and both tiles of H', S' (the mirror one transposed through LDS), and writes the
+// result to both (on a diagonal tile, its upper triangle to both halves). HW and SW come out
+// exactly symmetric; every element of H', S' and of the upper halves is read once.
+__global__ __launch_bounds__(NT) void k_update_mm_sym(double* HW, double* SW, const double* H1,
+                                                      const double* S1, const double* H2,
+                                                      const double* S2, int M, double* partials,
+                                                      const DevState* st) {
+  if (st->done) return;
+  __shared__ double th[32][33], ts[32][33], oh[32][33], os[32][33];
+  __shared__ double sh[NT / 64];
+  const double x = st->x;
+  double tr = 0.0, f = 0.0, trs = 0.0;
+  const int T = (M + 31) / 32;
+  const int npairs = T * (T + 1) / 2;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
+    int bi = 0, rem = p;
+    while (rem >= T - bi) {
+      rem -= T - bi;
+      ++bi;
+    }
+    const int bj = bi + rem;
+    const int i0 = bi * 32, j0 = bj * 32;
+    const bool diag = bi == bj;
+    __syncthreads();
+    // th[c][r] = H'[j0 + c][i0 + r], the transposed partner of output (i0 + r, j0 + c)
+    for (int rr = ty; rr < 32; rr += 8) {
+      const int i = j0 + rr, j = i0 + tx;
+      const bool in = i < M && j < M;
+      th[rr][tx] = in ? H1[(int64_t)i * M + j] : 0.0;
+      ts[rr][tx] = in ? S1[(int64_t)i * M + j] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int i = i0 + r, j = j0 + tx;
+      if (i < M && j < M && (!diag || r <= tx)) {
+        const int64_t e = (int64_t)i * M + j;
+        const double hw = HW[e] + x * H1[e] + x * th[tx][r] + x * x * H2[e];
+        const double sw = SW[e] + x * S1[e] + x * ts[tx][r] + x * x * S2[e];
+        HW[e] = hw;
+        SW[e] = sw;
+        oh[r][tx] = hw;
+        os[r][tx] = sw;
+        if (diag && r == tx) {
+          tr += hw;
+          trs += sw;
+          f += sw * hw;
+        } else {
+          f += 2.0 * sw * hw;
+        }
+      }
+    }
+    __syncthreads();
+    // mirror: element (j0 + rr, i0 + tx) = output (i0 + tx, j0 + rr)
+    for (int rr = ty; rr < 32; rr += 8) {
+      const int i = j0 + rr, j = i0 + tx;
+      if (i < M && j < M && (!diag || tx < rr)) {
+        const int64_t e = (int64_t)i * M + j;
+        HW[e] = oh[tx][rr];
+        SW[e] = os[tx][rr];
+      }
+    }
+  }
+  const double a = block_sum(tr, sh);
+  const double b = block_sum(f, sh);
+  const double c = block_sum(trs, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 3 + 0] = a;
+    partials[blockIdx.x * 3 + 1] = b;
+    partials[blockIdx.x * 3 + 2] = c;
+  }
 }
 
 __device__ __forceinline__ void f_update_final(const double* partials, int nb, int M, DevState* st,
@@ -1161,8 +1230,9 @@ OMM_UPDATE_SPLIT(double, float)
 hipError_t update_subspace(double* HW, double* SW, const double* H1, const double* S1,
                            const double* H2, const double* S2, int M, double* partials,
                            DevState* st, double* trace, hipStream_t s) {
-  const int nb = tile_blocks(M);
-  hipLaunchKernelGGL(k_update_mm, dim3(nb), dim3(NT), 0, s, HW, SW, H1, S1, H2, S2, M, partials,
+  const int T = (M + 31) / 32, npairs = T * (T + 1) / 2;
+  const int nb = npairs < RED_BLOCKS ? npairs : RED_BLOCKS;
+  hipLaunchKernelGGL(k_update_mm_sym, dim3(nb), dim3(NT), 0, s, HW, SW, H1, S1, H2, S2, M, partials,
                      st);
   hipLaunchKernelGGL(k_update_final, dim3(1), dim3(NT), 0, s, partials, nb, M, st, trace);
   return hipGetLastError();
