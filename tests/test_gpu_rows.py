@@ -162,8 +162,10 @@ def test_grouped_batch_matches_single_system_runs(torch):
 
 
 def test_full_size_first_line_searches_match_oracle(torch):
-    """N=13000, M=2000 in the benchmark's launch configuration: the first line search and the
-    state it leaves (C, SW) against the oracle; SW against C S C^T (any-size property)."""
+    """N=13000, M=2000: the first line search and the state it leaves (C, SW) against the oracle
+    in FP64, then the benchmark's BF16 scheme with the FP64 state in its launch configuration:
+    the step against the oracle's element by element, HW and SW after the resynchronization
+    against C Hs C^T and C S C^T on sampled rows (any-size properties)."""
     from paper_1312_1549_amd import OMM
 
     s = config_system("c3", 0)
@@ -188,5 +190,31 @@ def test_full_size_first_line_searches_match_oracle(torch):
     bf.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=1)
     tb = bf.energy_trace()
     assert abs(tb[1] - tr[1]) <= 1e-4 * abs(tr[1])
+    # the benchmark's scheme (BF16 products on the FP64 state, FP32 G, PG, HD, SD, autotuned
+    # stream-K tiles): one line search, which the call closes with an FP64 resynchronization
+    _say(f"full size c3 N={s.N} M={s.M} bf16x3 with fp64 state, 1 line search")
+    mx = OMM(s.N, s.M, precision="bf16x3", refine=True)
+    mx.set_HS(dev["H"], dev["S"], dev["T"])
+    mx.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=1)
+    tm = mx.energy_trace()
+    Cm = mx.get_C()
+    HWm, SWm = mx.subspace()
+    assert abs(tm[0] - tr[0]) <= 1e-11 * abs(tr[0])  # initial products in FP64
+    # D is rounded to bf16 and P applied as its bf16 rounding, so the step x D follows the FP64
+    # step to a few parts in a thousand (a CPU emulation of exactly those roundings at this size
+    # gives 2.0e-3 in Frobenius norm and 4.2e-3 of the largest element)
+    step_ref, step = ref.C - C0, Cm - C0
+    assert np.linalg.norm(step - step_ref) <= 5e-3 * np.linalg.norm(step_ref)
+    assert np.max(np.abs(step - step_ref)) <= 1e-2 * np.max(np.abs(step_ref))
+    assert tm[1] < tm[0]
+    assert abs(tm[1] - ref.energies[1]) <= 1e-3 * abs(tr[0] - ref.energies[1])
+    # after the resynchronization HW, SW and the energy are the FP64 functions of the returned C
+    Hs = oracle.shifted_hamiltonian(s.H, s.S, s.eta)
+    HW_rows = (Cm[rows] @ Hs) @ Cm.T
+    SW_rows = (Cm[rows] @ s.S) @ Cm.T
+    assert np.max(np.abs(HWm[rows] - HW_rows)) <= 1e-10 * np.max(np.abs(HW_rows))
+    assert np.max(np.abs(SWm[rows] - SW_rows)) <= 1e-10 * np.max(np.abs(SW_rows))
+    assert abs(mx.energy() - oracle.functional(HWm, SWm)) <= 1e-12 * abs(mx.energy())
+    assert abs(tm[1] - mx.energy()) <= 1e-12 * abs(mx.energy())
     ref_E = json.loads((ROOT / "tests" / "golden" / "c3_reference.json").read_text())["E_min"]
     assert tr[1] > ref_E  # variational: never below the closed-form minimum
