@@ -824,17 +824,23 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     op.A[1] = a2.p; op.Alo[1] = a2.lo; op.lda[1] = a2.ld;
     op.B[1] = b2.p; op.Blo[1] = b2.lo; op.ldb[1] = b2.ld;
     op.K[1] = M;
-    // G's planes for the preconditioner product, from the epilogue
-    if (fuse && c->p_kind > 0) out_planes(op, c->G_p);
+    // G's bf16 plane for the preconditioner product, from the epilogue (the product takes G
+    // rounded to bf16: no lo plane)
+    if (fuse && c->p_kind > 0) {
+      out_planes(op, c->G_p);
+      op.Clo = nullptr;
+    }
     TRY(gemm(c, d, &op, 1, done));
     TRY(fill_pairs(c, Gout, tg, N, N, fuse && c->p_kind > 0 ? &c->G_p : nullptr));
   }
   TRY(prof_mark(c));
   // BF16x3: the preconditioner is applied as its bf16 rounding (the hi plane of P, a symmetric
-  // matrix of its own) and the search direction is rounded to bf16 when it is formed, so every
-  // product with P or D takes two MFMA products instead of three (same accuracy: the rounded
-  // operand is exact).
-  const int cP = bf ? CBF16X2B : compute, cD = bf ? CBF16X2A : compute;
+  // matrix of its own) to the bf16 rounding of G, a single MFMA product, and the search direction
+  // is rounded to bf16 when it is formed, so every product with D takes two MFMA products
+  // instead of three (same accuracy: the rounded operand is exact). PG only shapes the search
+  // direction (the line search is exact along whatever D results), and a relative error of
+  // 2^-9 in it stays relative as G shrinks.
+  const int cP = bf ? CBF16X1 : compute, cD = bf ? CBF16X2A : compute;
   T* PG = G;
   if (c->p_kind > 0) {
     if (bf && !fuse) {

@@ -86,8 +86,8 @@ bool dma_ok(const GemmDesc& d, const GemmOp* ops, int nops) {
       constexpr int64_t lim = (int64_t)1 << 31;
       if ((int64_t)op.M * op.lda[g] >= lim || (int64_t)op.N * op.ldb[g] >= lim) return false;
       if (!al(op.A[g]) || !al(op.B[g])) return false;
-      if (d.compute != CBF16X2A && !al(op.Alo[g])) return false;
-      if (d.compute != CBF16X2B && !al(op.Blo[g])) return false;
+      if (!one_plane_a(d.compute) && !al(op.Alo[g])) return false;
+      if (!one_plane_b(d.compute) && !al(op.Blo[g])) return false;
     }
   }
   return true;
@@ -97,7 +97,8 @@ bool dma_ok(const GemmDesc& d, const GemmOp* ops, int nops) {
 namespace {
 sk_fn pick_sk(const GemmDesc& d) {
   if (d.compute == CBF16X3) return pick_sk_bf16x3(d);
-  if (d.compute == CBF16X2A || d.compute == CBF16X2B) return pick_sk_bf16x2(d);
+  if (d.compute == CBF16X2A || d.compute == CBF16X2B || d.compute == CBF16X1)
+    return pick_sk_bf16x2(d);
   return nullptr;
 }
 }  // namespace
@@ -108,7 +109,8 @@ bool gemm_supported(const GemmDesc& d) {
   if (d.compute == CF64) return pick_f64(d) != nullptr;
   if (d.compute == CF32) return pick_f32(d) != nullptr;
   if (d.compute == CBF16X3) return pick_bf16x3(d) != nullptr;
-  if (d.compute == CBF16X2A || d.compute == CBF16X2B) return pick_bf16x2(d) != nullptr;
+  if (d.compute == CBF16X2A || d.compute == CBF16X2B || d.compute == CBF16X1)
+    return pick_bf16x2(d) != nullptr;
   return false;
 }
 
@@ -185,7 +187,8 @@ hipError_t launch_products(const GemmDesc& d, const GemmOp* ops, int nops, const
   if (dd.compute == CF64) fn = pick_f64(dd);
   else if (dd.compute == CF32) fn = pick_f32(dd);
   else if (dd.compute == CBF16X3) fn = pick_bf16x3(dd);
-  else if (dd.compute == CBF16X2A || dd.compute == CBF16X2B) fn = pick_bf16x2(dd);
+  else if (dd.compute == CBF16X2A || dd.compute == CBF16X2B || dd.compute == CBF16X1)
+    fn = pick_bf16x2(dd);
   if (!fn) return hipErrorInvalidValue;
   const int bm = tile_bm(dd.tile, dd.compute), bn = tile_bn(dd.tile, dd.compute);
   const int tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);

@@ -1,6 +1,7 @@
 // Two-product BF16 MFMA GEMM instantiations on pre-split bf16 planes: one operand holds exact
 // bf16 values (its hi plane alone), the other a hi/lo pair. Used for products with the search
-// direction (A) and with the preconditioner (B) in the BF16x3 scheme.
+// direction (A) in the BF16x3 scheme. The one-product mode (both operands single planes, FP32
+// output) applies the preconditioner's bf16 rounding to the gradient's.
 #include "omm_gemm_impl.h"
 
 namespace omm {
@@ -20,6 +21,9 @@ gemm_fn pick_mode(const GemmDesc& d) {
 gemm_fn pick_bf16x2(const GemmDesc& d) {
   if (d.compute == CBF16X2A) return pick_mode<CBF16X2A>(d);
   if (d.compute == CBF16X2B) return pick_mode<CBF16X2B>(d);
+  if (d.compute == CBF16X1 && d.la == KC && d.lb == KC && d.ta == T_BF16P && d.tb == T_BF16P &&
+      d.tc == T_F32 && d.tx == T_F32)
+    return pick_tile<CBF16X1, unsigned short, unsigned short, float, float, KC, KC>(d.tile);
   return nullptr;
 }
 
@@ -36,6 +40,7 @@ sk_fn pick_sk_mode(const GemmDesc& d) {
 sk_fn pick_sk_bf16x2(const GemmDesc& d) {
   if (d.compute == CBF16X2A) return pick_sk_mode<CBF16X2A>(d);
   if (d.compute == CBF16X2B) return pick_sk_mode<CBF16X2B>(d);
+  // no stream-K for the one-product mode: its instantiation exceeds the register file (spills)
   return nullptr;
 }
 

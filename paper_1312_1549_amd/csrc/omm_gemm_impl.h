@@ -20,6 +20,7 @@
 //            while a tile is staged.
 //   CBF16X2A / CBF16X2B  the same with A (B) exactly representable in bf16: only its hi plane
 //            is staged and two products remain (hi*lo + hi*hi).
+//   CBF16X1  both operands single bf16 planes: one product hi*hi.
 #pragma once
 
 #include <type_traits>
@@ -142,6 +143,8 @@ template <>
 struct ModeTraits<CBF16X2A> : ModeTraits<CBF16X3> {};
 template <>
 struct ModeTraits<CBF16X2B> : ModeTraits<CBF16X3> {};
+template <>
+struct ModeTraits<CBF16X1> : ModeTraits<CBF16X3> {};
 
 // Global -> register staging of one operand tile (R rows x BK), `NV` vectors of VEC per thread.
 // KC: vector = VEC consecutive k of one row. RC: vector = VEC consecutive rows of one k.
@@ -392,7 +395,8 @@ __device__ __forceinline__ void store_out(const GemmOp& op, int row, int col, do
     const unsigned short h = bf16_rne((float)w);
     const int64_t e = (int64_t)row * op.ldp + col;
     static_cast<unsigned short*>(op.Chi)[e] = h;
-    static_cast<unsigned short*>(op.Clo)[e] = bf16_rne((float)(w - (double)bf16_val(h)));
+    if (op.Clo)  // null: the next product reads the hi plane alone
+      static_cast<unsigned short*>(op.Clo)[e] = bf16_rne((float)(w - (double)bf16_val(h)));
   }
 }
 
@@ -432,7 +436,7 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
                                           double* ws, int z, int nops) {
   constexpr int NT = WM * WN * 64;
   constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
-  constexpr bool ONE_A = MODE == CBF16X2A, ONE_B = MODE == CBF16X2B;
+  constexpr bool ONE_A = one_plane_a(MODE), ONE_B = one_plane_b(MODE);
   typedef Stager<MODE, TA, LA, BM, BK, NT, SWZ, ONE_A> SA;
   typedef Stager<MODE, TB, LB, BN, BK, NT, SWZ, ONE_B> SB;
   typedef typename ModeTraits<MODE>::lds_t lds_t;
@@ -599,7 +603,7 @@ template <int MODE, int NS, typename USER>
 __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int tn, int g0, int g1,
                                                   f4 (&acc)[DMA_TM][DMA_TN]) {
   constexpr int WM = 2, TM = DMA_TM, TN = DMA_TN, NT = 512, BK = DMA_BK, RS = DMA_BK;
-  constexpr bool ONE_A = MODE == CBF16X2A, ONE_B = MODE == CBF16X2B;
+  constexpr bool ONE_A = one_plane_a(MODE), ONE_B = one_plane_b(MODE);
   constexpr int NBA = ONE_A ? 1 : 2, NBB = ONE_B ? 1 : 2, NPL = NBA + NBB;
   constexpr int DPS = NPL * (DMA_BM * BK * 2 / 1024) / 8;  // 1 KB wave loads per wave per stage
   static_assert(is_bf16_mode(MODE), "direct-to-LDS path: bf16 planes only");
@@ -705,7 +709,8 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
       // from LDS while the MFMAs of pair p run, so a wave waits on LDS once per stage (for its
       // B fragments and first pair) instead of once per pair.
       constexpr int PAIR = 2, NPAIR = TM / PAIR, NAR = ONE_A ? 1 : 2;
-      constexpr int NPROD = (ONE_A || ONE_B) ? 2 : 3, NBR = TN * (ONE_B ? 1 : 2);
+      constexpr int NPROD = (ONE_A && ONE_B) ? 1 : (ONE_A || ONE_B) ? 2 : 3;
+      constexpr int NBR = TN * (ONE_B ? 1 : 2);
       static_assert(TM % PAIR == 0, "row blocks come in pairs");
       bf8 ah[2][PAIR], al[2][PAIR], bh[TN], bl[TN];
       auto load_pair = [&](int p) {

@@ -32,9 +32,12 @@ enum Layout : int { KC = 0, RC = 1 };
 
 // CBF16X3: both operands are hi/lo bf16 plane pairs, three products per K step (lo*hi, hi*lo,
 // hi*hi). CBF16X2A / CBF16X2B: A (B) holds exact bf16 values in its hi plane alone, so two
-// products (hi*lo + hi*hi) carry the same accuracy.
-enum Compute : int { CF64 = 0, CF32 = 1, CBF16X3 = 2, CBF16X2A = 3, CBF16X2B = 4 };
+// products (hi*lo + hi*hi) carry the same accuracy. CBF16X1: both operands are single planes of
+// exact bf16 values, one product (the product of the two bf16 matrices, FP32 sums).
+enum Compute : int { CF64 = 0, CF32 = 1, CBF16X3 = 2, CBF16X2A = 3, CBF16X2B = 4, CBF16X1 = 5 };
 constexpr bool is_bf16_mode(int m) { return m >= CBF16X3; }
+constexpr bool one_plane_a(int m) { return m == CBF16X2A || m == CBF16X1; }
+constexpr bool one_plane_b(int m) { return m == CBF16X2B || m == CBF16X1; }
 
 // T_BF16P: a pair of bf16 planes (hi, lo) with a = hi + lo, pointers in A/Alo (B/Blo).
 enum ElemType : int { T_F64 = 0, T_F32 = 1, T_BF16P = 2 };
