@@ -40,7 +40,10 @@ sk_fn pick_sk_mode(const GemmDesc& d) {
 sk_fn pick_sk_bf16x2(const GemmDesc& d) {
   if (d.compute == CBF16X2A) return pick_sk_mode<CBF16X2A>(d);
   if (d.compute == CBF16X2B) return pick_sk_mode<CBF16X2B>(d);
-  // no stream-K for the one-product mode: its instantiation exceeds the register file (spills)
+  // (its instantiation spills a few per-work-item values to scratch memory, outside the K loop)
+  if (d.compute == CBF16X1 && d.la == KC && d.lb == KC && d.ta == T_BF16P && d.tb == T_BF16P &&
+      d.tc == T_F32 && d.tx == T_F32)
+    return pick_sk_kernel<CBF16X1, float, float>();
   return nullptr;
 }
 
