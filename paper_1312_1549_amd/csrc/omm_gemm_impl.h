@@ -591,6 +591,11 @@ __device__ __forceinline__ void wait_vm_lgkm0() {
 }
 
 constexpr int DMA_TM = 8, DMA_TN = 4;  // 16 x 16 blocks per wave (wave grid 2 x 4)
+// LDS stages of the direct-to-LDS tile: 64 KB each with three products, 48 KB with two, 32 KB
+// with one, in 160 KB
+constexpr int dma_stages(int mode) {
+  return mode == CBF16X3 ? 2 : mode == CBF16X1 ? 4 : 3;
+}
 template <int KIND, typename TC, typename TX>
 struct DmaUser {
   static constexpr int kind = KIND;  // 0: one tile per workgroup, 1: stream-K
@@ -689,9 +694,10 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
     for (int st = 0; st < NS - 1; ++st)
       if (st < nst) issue(st);
     for (int t = 0; t < nst; ++t) {
-      // this wave's loads of stage t have landed (those of stage t + 1 may still be in flight),
-      // then every wave's have
-      if (NS > 2 && t + 1 < nst && full(t + 1)) wait_vm_lgkm0<(NS > 2 ? DPS : 0)>();
+      // this wave's loads of stage t have landed (those of the issued stages after it, up to
+      // t + NS - 2, may still be in flight), then every wave's have
+      if (NS > 3 && t + 2 < nst && full(t + 2)) wait_vm_lgkm0<(NS > 3 ? 2 * DPS : 0)>();
+      else if (NS > 2 && t + 1 < nst && full(t + 1)) wait_vm_lgkm0<(NS > 2 ? DPS : 0)>();
       else wait_vm_lgkm0<0>();
       __builtin_amdgcn_s_barrier();
       if (t + NS - 1 < nst) issue(t + NS - 1);
@@ -999,7 +1005,7 @@ typedef void (*sk_fixup_fn)(GemmBatch, const int*, SkArgs, int, const float*);
 
 template <int MODE, typename TC, typename TX>
 sk_fn pick_sk_kernel() {
-  return gemm_kernel_sk<MODE, TC, TX, MODE == CBF16X3 ? 2 : 3>;
+  return gemm_kernel_sk<MODE, TC, TX, dma_stages(MODE)>;
 }
 
 // Tile shapes (macro tile M x N): 0: 128x128 (4 waves), 1: 64x64 (4 waves, 2 workgroups per
@@ -1055,7 +1061,7 @@ gemm_fn pick_tile(int tile) {
     case 5:
       if constexpr (is_bf16_mode(MODE) && std::is_same<TA, unsigned short>::value &&
                     std::is_same<TB, unsigned short>::value && LA == KC && LB == KC)
-        return gemm_kernel_dma<MODE, TC, TX, MODE == CBF16X3 ? 2 : 3>;
+        return gemm_kernel_dma<MODE, TC, TX, dma_stages(MODE)>;
       else
         return nullptr;
     default: return nullptr;
