@@ -77,6 +77,8 @@ def test_fp64_c1_matches_oracle_and_closed_form(lib_ok, c1, tau):
     assert abs(it - ref.iterations) <= max(5, 0.1 * ref.iterations)
     HW, SW = solver.subspace()
     assert np.max(np.abs(SW - np.eye(s.M))) < 1e-4
+    # the incremental update of HW, SW (Eq. 16) writes each upper element to its mirror
+    assert np.array_equal(HW, HW.T) and np.array_equal(SW, SW.T)
     # outputs: density and energy-density matrices of the GPU's own C, element by element
     C = solver.get_C()
     SW_c = C @ s.S @ C.T
