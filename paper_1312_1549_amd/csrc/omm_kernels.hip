@@ -36,6 +36,21 @@ __device__ __forceinline__ double sum_partials(const double* partials, int nb, i
   return block_sum(v, sh);
 }
 
+// sum_partials of columns 0..W-1 of rows of width W, in the same per-column order, with the
+// loads of all columns in flight together.
+template <int W>
+__device__ __forceinline__ void sum_partials_all(const double* partials, int nb, double* sh,
+                                                 double (&out)[W]) {
+  double v[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += NT)
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[k] += partials[b * W + k];
+#pragma unroll
+  for (int k = 0; k < W; ++k) out[k] = block_sum(v[k], sh);
+}
+
 int red_blocks(int64_t n) {
   int64_t b = (n + NT - 1) / NT;
   if (b > RED_BLOCKS) b = RED_BLOCKS;
@@ -548,7 +563,7 @@ __device__ __forceinline__ void f_line_final(const double* partials, int nb, Dev
   if (st->done) return;
   __shared__ double sh[NT / 64];
   double s[NCOEF];
-  for (int k = 0; k < NCOEF; ++k) s[k] = sum_partials(partials, nb, NCOEF, k, sh);
+  sum_partials_all<NCOEF>(partials, nb, sh, s);
   if (threadIdx.x != 0) return;
   double a[5];
   a[0] = 4.0 * s[0] - 2.0 * s[3];
