@@ -260,6 +260,47 @@ def test_cholesky_reduction_follows_s_inverse_preconditioning(c1):
     assert err < 1e-9
 
 
+# ---- the kinetic-energy preconditioner (Sec. 2.4, Eq. 17) ------------------------------------
+
+def _precon_pin_error(precon_fn=None):
+    """Worst relative error of P(S, T, tau) against two facts fixed independently of Eq. 17's
+    matrix inverse: (a) Sec. 2.4's limit tau -> infinity, where P becomes S^-1 (LAPACK inverse
+    of S alone); (b) the spectral closed form for commuting S = Q diag(s) Q^T and
+    T = Q diag(t) Q^T, where P = Q diag(1 / (s_i + t_i / tau)) Q^T, i.e. each kinetic-energy
+    eigendirection is damped by tau / (tau s_i + t_i)."""
+    fn = precon_fn or omm.preconditioner
+    rng = np.random.default_rng(21)
+    n = 24
+    A = rng.standard_normal((n, n))
+    S = A @ A.T / n + 0.5 * np.eye(n)
+    T = _rand_sym(rng, n)
+    worst = 0.0
+    P = fn(S, T, 1e10)
+    Si = np.linalg.inv(S)
+    worst = max(worst, np.linalg.norm(P - Si) / np.linalg.norm(Si))
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = rng.uniform(0.2, 2.0, n)
+    t = rng.uniform(0.1, 30.0, n)  # kinetic eigenvalues: positive, spread over two decades
+    Sc = (Q * s) @ Q.T
+    Tc = (Q * t) @ Q.T
+    for tau in (0.5, 3.0, 10.0):
+        ref = (Q * (1.0 / (s + t / tau))) @ Q.T
+        worst = max(worst, np.linalg.norm(fn(Sc, Tc, tau) - ref) / np.linalg.norm(ref))
+    return float(worst)
+
+
+def test_preconditioner_limit_and_spectral_closed_form():
+    """Eq. 17 pinned without re-typing it: the tau = infinity limit of Sec. 2.4 and the
+    commuting-pencil closed form; tau = inf and tau <= 0 select S^-1 and no preconditioning."""
+    assert _precon_pin_error() < 1e-8
+    rng = np.random.default_rng(22)
+    A = rng.standard_normal((10, 10))
+    S = A @ A.T / 10 + np.eye(10)
+    assert np.allclose(omm.preconditioner(S, None, math.inf) @ S, np.eye(10), atol=1e-12)
+    assert omm.preconditioner(S, None, 0.0) is None
+    assert omm.preconditioner(S, None, -1.0) is None
+
+
 # ---- stopping rule (Eq. 18) -------------------------------------------------------------------
 
 def test_stopping_rule_uses_magnitudes():
@@ -331,3 +372,13 @@ def test_pins_catch_planted_mistakes(c1):
     finally:
         omm.polak_ribiere_beta = orig
     assert err > 1e-6
+
+    # the kinetic matrix scaled by tau instead of 1/tau, or subtracted: Eq. 17 misread
+    def precon_tau_times_T(S, T, tau):
+        return np.linalg.inv(S + tau * T)
+
+    def precon_minus_T(S, T, tau):
+        return np.linalg.inv(S - T / tau)
+
+    assert _precon_pin_error(precon_tau_times_T) > 1e-2
+    assert _precon_pin_error(precon_minus_T) > 1e-2
