@@ -2,13 +2,20 @@
 
 Workload (default): 1000 atoms on a 10x10x10 lattice (a = 3.0 bohr, r_c = 8 bohr), 13 orbitals
 per atom -> N = 13000 basis orbitals, M = 2000 Wannier functions, eta = 0, tau = 10, synthetic
-finite-range S/T/H (seeded). A "step" is one CG line search (gradient, preconditioning,
-Polak-Ribiere direction, operator products, projections, quartic coefficients + line minimum,
-updates + energy + stopping test); inputs are resident in HBM before the timed region.
+finite-range S/T/H (seeded); inputs are resident in HBM before the timed region.
 
-Prints ONE JSON line: the headline value is mixed-precision (BF16x3 MFMA, FP64 reductions)
-line searches per second; it also carries the FP64 rate, time to a converged energy for both,
-the roofline of the dominant kernel and the CPU oracle timed on a bounded sample.
+A "step" is one pass over every stage of the path. In the mixed-precision scheme (the default)
+that is one resynchronization period: `--resync` (80) CG line searches (gradient,
+preconditioning, Polak-Ribiere direction, operator products, projections, quartic coefficients +
+line minimum, updates + energy) with bf16 MFMA products on the FP64 state, closed by the FP64
+recomputation of the state from C that the scheme performs every `--resync` line searches. The
+timed window therefore always holds whole periods, and `value` (line searches per second)
+includes each resynchronization's full cost. With `--precision fp64` or `fp32` a step is one
+line search.
+
+Prints ONE JSON line: the headline value, the FP64 and FP32 rates, time to a converged energy for
+the mixed scheme and FP64, the roofline of the dominant kernel, the batched workload (64 systems)
+at the mixed-precision bar, and the CPU oracle timed on a bounded sample.
 """
 
 from __future__ import annotations
@@ -74,7 +81,11 @@ def measured_traffic(workload, precision):
 
 
 def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=False, resync=20,
-                    flavour="dense", sparse=False):
+                    flavour="dense", sparse=False, per_step=1):
+    """Wall time of `steps` steps of `per_step` line searches each, after `warmup` steps. With the
+    mixed scheme (refine) per_step is the resynchronization interval, so the window holds whole
+    periods; the run restarts from C0 after the warm-up (setup outside the window) and the
+    window's resynchronizations are counted from the scheme's checkpoints."""
     solver = OMM(s.N, s.M, precision=prec, refine=refine, resync=resync, flavour=flavour,
                  sparse=sparse)
     solver.set_HS(dev["H"], dev["S"], dev["T"])
@@ -82,12 +93,16 @@ def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=
     solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # setup only
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    solver.iterate(warmup)
+    solver.iterate(warmup * per_step)
+    solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # restart from C0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    solver.iterate(steps)
+    solver.iterate(steps * per_step)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    resyncs = None
+    if prec == "bf16x3" and refine:
+        resyncs = len(solver.checkpoints()[0]) - 1  # the first checkpoint is the start
     stages = None
     if prof_steps > 0:
         solver.set_profiling(True)
@@ -97,7 +112,7 @@ def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=
         stages = {k: v / max(n, 1) for k, v in stages.items()}
         solver.set_profiling(False)
     solver.close()
-    return wall, setup_s, stages
+    return wall, setup_s, stages, resyncs
 
 
 def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, resync, flavour="dense",
@@ -164,7 +179,10 @@ def complex_bench(args, torch):
         torch.cuda.synchronize()
         return sol
 
-    for prec, steps in (("bf16x3", args.steps), ("fp64", max(3, args.steps // 4))):
+    # bf16 scheme: whole resynchronization periods, FP64: 20 line searches; after 2 untimed
+    # line searches (they tune the GEMM tiles), so the bf16 window holds one resynchronization
+    # per period
+    for prec, steps in (("bf16x3", max(2, args.steps // 4) * args.resync), ("fp64", 20)):
         sol = solver_for(prec)
         sol.iterate(2)
         torch.cuda.synchronize()
@@ -172,6 +190,7 @@ def complex_bench(args, torch):
         sol.iterate(steps)
         torch.cuda.synchronize()
         out[f"{prec}_iters_per_s"] = steps / (time.perf_counter() - t0)
+        out[f"{prec}_line_searches_timed"] = steps
         sol.close()
         log(f"complex {prec}: {out[prec + '_iters_per_s']:.2f} iters/s")
     E_ref = reference_energy("c5_k0.3", s)
@@ -220,24 +239,61 @@ def complex_bench(args, torch):
     return out
 
 
-def cpu_baseline(s, C0, iters):
-    from oracle import omm as oracle
-
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
 
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
+        return max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
     except Exception:
-        threads = os.cpu_count()
-    P = oracle.preconditioner(s.S, s.T, s.tau)  # setup, not timed
+        return os.cpu_count()
+
+
+def _oracle_rate(oracle, s, C0, P, warm, iters):
+    """Line searches per second of the oracle over `iters` line searches after `warm` (setup and
+    the warm-up outside the window)."""
     stamps = []
-    oracle.minimize(s.H, s.S, s.T, C0, s.eta, s.tau, 0.0, iters, P=P, use_given_P=True,
+    oracle.minimize(s.H, s.S, s.T, C0, s.eta, s.tau, 0.0, warm + iters, P=P, use_given_P=True,
                     callback=lambda k, E: stamps.append(time.perf_counter()))
-    per = (stamps[-1] - stamps[0]) / iters
-    return {"value": 1.0 / per, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{iters} FP64 line searches of the NumPy oracle on the same N={s.N}, "
-                      f"M={s.M} inputs after its untimed setup (P inverse, initial products); "
-                      f"host BLAS threads={threads}, os.cpu_count()={os.cpu_count()}"}
+    return iters / (stamps[warm + iters] - stamps[warm])
+
+
+def cpu_baseline(s, C0, iters, warm, closed_form=False):
+    """The CPU oracle on the host cores: the bench workload on all BLAS threads, plus the
+    2048-orbital workload on all threads and on one (a single-threaded line search of the bench
+    workload would take about a minute), and optionally LAPACK's closed form of the bench
+    workload (the exact-energy baseline)."""
+    from oracle import brute, omm as oracle
+    from synth import config_system, start_coefficients
+
+    threads = _blas_threads()
+    P = oracle.preconditioner(s.S, s.T, s.tau)  # setup, not timed
+    rate = _oracle_rate(oracle, s, C0, P, warm, iters)
+    out = {"value": rate, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{iters} FP64 line searches of the NumPy oracle on the same N={s.N}, M={s.M} "
+                     f"inputs after {warm} untimed warm-up line searches and its untimed setup (P "
+                     f"inverse, initial products); host BLAS threads={threads}, "
+                     f"os.cpu_count()={os.cpu_count()}"}
+    del P
+    c2 = config_system("c2", 0)
+    C02 = start_coefficients(c2.S, c2.M, 1)
+    P2 = oracle.preconditioner(c2.S, c2.T, c2.tau)
+    out["workload_2048"] = {"workload": WORKLOADS["c2"],
+                            "all_threads_iters_per_s": _oracle_rate(oracle, c2, C02, P2, 1, 4)}
+    try:
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=1):
+            out["workload_2048"]["one_thread_iters_per_s"] = _oracle_rate(oracle, c2, C02, P2, 1, 4)
+    except Exception as e:  # threadpoolctl missing: no single-thread figure
+        out["workload_2048"]["one_thread_error"] = str(e)
+    if closed_form:
+        t0 = time.perf_counter()
+        w = brute.generalized_eigh_lapack(s.H, s.S, s.M + 1)[0]
+        out["closed_form_s"] = time.perf_counter() - t0
+        out["closed_form_E"] = brute.closed_form_energy(w, s.M, s.eta)
+        out["closed_form_note"] = ("LAPACK generalized symmetric-definite eigensolver, lowest "
+                                   "M + 1 eigenvalues, all BLAS threads")
+    return out
 
 
 def summarize_rocprof(trace_csv, top=12):
@@ -261,47 +317,82 @@ def summarize_rocprof(trace_csv, top=12):
     return "\n".join(out)
 
 
-def batched_bench(args):
-    """Batched systems: cold solve to tol 1e-10, then an SCF-like warm start."""
+def batched_bench(args, standalone=False):
+    """Batched systems (64, N = 256..2048): FP32 grouped phase to 1e-9 then the FP64 grouped
+    phase to tol 1e-12, cold, then an SCF-like warm start after H += 1e-3 sym(N(0,1)); the
+    energies against the closed forms stored by tests/golden/make_golden.py (when they match the
+    generated inputs)."""
     import torch
     from paper_1312_1549_amd import OMMBatch, flops_per_iteration
     from synth import batched_systems, perturb_hamiltonian, start_coefficients
 
-    log("generating 64 systems")
+    t0 = time.perf_counter()
+    log("batched: generating 64 systems")
     systems = batched_systems(count=64)
     C0s = [start_coefficients(x.S, x.M, 1000 + i) for i, x in enumerate(systems)]
-    b = OMMBatch([x.N for x in systems], [x.M for x in systems])
+    gen_s = time.perf_counter() - t0
+    ref = None
+    f = ROOT / "tests" / "golden" / "c4_reference.json"
+    if f.exists():
+        rows = json.loads(f.read_text())["systems"]
+        if len(rows) == len(systems) and all(
+                r["N"] == x.N and abs(r["trace_H"] - float(np.trace(x.H))) <= 1e-9 * abs(r["trace_H"])
+                for r, x in zip(rows, systems)):
+            ref = rows
+    tol = 1e-12
+    b = OMMBatch([x.N for x in systems], [x.M for x in systems], precision="fp32", refine=True)
     for i, x in enumerate(systems):
         b.set_HS(i, x.H, x.S, x.T)
     etas, taus = [x.eta for x in systems], [x.tau for x in systems]
-    b.minimize(C0s, etas, taus, 1e-10, 10)  # warm-up: setup, autotune, graph
+    b.minimize(C0s, etas, taus, tol, 10)  # warm-up: setup, autotune, graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = b.minimize(C0s, etas, taus, 1e-10, 5000)
+    st = b.minimize(C0s, etas, taus, tol, 5000)
     torch.cuda.synchronize()
     cold = time.perf_counter() - t0
-    it = b.iterations()
+    it32, it64 = b.phase_iterations()
+    it = it32 + it64
+    E = b.energies()
     flops = sum(int(k) * flops_per_iteration(x.N, x.M) for k, x in zip(it, systems))
-    log(f"cold: {cold:.2f}s, {int(it.sum())} line searches, max {int(it.max())}")
+    log(f"batched cold: {cold:.2f}s, {int(it.sum())} line searches ({int(it32.sum())} fp32 + "
+        f"{int(it64.sum())} fp64)")
+    out = {"workload": WORKLOADS["c4"], "precision": "fp32 grouped phase to 1e-9, then fp64 "
+           "grouped phase to tol 1e-12 (fp64 reductions throughout)",
+           "line_searches_per_s": float(it.sum()) / cold, "systems_per_s": len(systems) / cold,
+           "algorithmic_tflops": flops / cold / 1e12, "cold_s": cold, "status": int(st),
+           "cold_line_searches": {"fp32": int(it32.sum()), "fp64": int(it64.sum()),
+                                  "max_per_system": int(it.max())},
+           "generation_s": gen_s}
+    if ref is not None:
+        err = np.abs(E - np.array([r["E_min"] for r in ref])) / np.abs([r["E_min"] for r in ref])
+        out["max_rel_err_vs_closed_form"] = float(err.max())
     Cs = [b.get_C(i) for i in range(len(systems))]
     for i, x in enumerate(systems):
         b.set_HS(i, perturb_hamiltonian(x.H, 200 + i), x.S, x.T)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.minimize(Cs, etas, taus, 1e-10, 5000)
+    stw = b.minimize(Cs, etas, taus, tol, 5000)
     torch.cuda.synchronize()
     warm = time.perf_counter() - t0
-    itw = b.iterations()
+    w32, w64 = b.phase_iterations()
+    out.update({"warm_s": warm, "warm_status": int(stw),
+                "warm_line_searches": {"fp32": int(w32.sum()), "fp64": int(w64.sum()),
+                                       "max_per_system": int((w32 + w64).max())}})
+    if ref is not None:
+        Ew = b.energies()
+        refw = np.array([r["E_min_warm"] for r in ref])
+        out["warm_max_rel_err_vs_closed_form"] = float((np.abs(Ew - refw) / np.abs(refw)).max())
+    b.close()
+    log(f"batched warm: {warm:.2f}s; max rel err cold {out.get('max_rel_err_vs_closed_form')} "
+        f"warm {out.get('warm_max_rel_err_vs_closed_form')}")
+    if not standalone:
+        return out
     return {
         "metric": "batched OMM CG line searches/sec (64 systems, N=256..2048)",
-        "value": float(it.sum()) / cold, "unit": "line searches/s", "n_gpus": 1,
+        "value": out["line_searches_per_s"], "unit": "line searches/s", "n_gpus": 1,
         "steps": int(it.max()), "warmup": 10, "ms_per_step": 1e3 * cold / max(1, int(it.max())),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
-        "data": "synthetic", "config": {"workload": WORKLOADS["c4"]},
-        "systems_per_s": len(systems) / cold, "algorithmic_tflops": flops / cold / 1e12,
-        "cold_s": cold, "cold_line_searches_total": int(it.sum()), "status": int(st),
-        "warm_s": warm, "warm_line_searches_total": int(itw.sum()),
-        "warm_line_searches_max": int(itw.max()),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64",
+        "data": "synthetic", "config": {"workload": WORKLOADS["c4"]}, "batched": out,
     }
 
 
@@ -326,12 +417,16 @@ def main():
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=80)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed steps (mixed scheme: resynchronization periods of --resync line "
+                         "searches each; fp64/fp32: line searches)")
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-converge", action="store_true", help="skip time-to-converged runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-closed-form", action="store_true",
+                    help="also time LAPACK's closed form of the workload on the host")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison rate")
     ap.add_argument("--no-cholesky", action="store_true",
                     help="skip the Cholesky-reduced flavour's rate and time to converged")
@@ -339,16 +434,18 @@ def main():
                     help="skip the block-sparse operator products' rate and time to converged")
     ap.add_argument("--no-complex", action="store_true",
                     help="skip the complex Hermitian (k-point) rates and time to converged")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batch")
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--resync", type=int, default=80)
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-warmup", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     if args.workload == "c4":
-        print(json.dumps(batched_bench(args)), flush=True)
+        print(json.dumps(batched_bench(args, standalone=True)), flush=True)
         return
 
     import torch
@@ -363,45 +460,55 @@ def main():
     torch.cuda.synchronize()
 
     flops = flops_per_iteration(s.N, s.M, preconditioned=s.tau > 0)
-    prof_steps = min(args.steps, 10)
-    mixed = args.precision != "fp64"
-    log(f"timing {args.precision}: warmup {args.warmup}, steps {args.steps}")
-    wall, setup_s, stages = time_iterations(OMM, torch, dev, s, args.precision, args.steps,
-                                            args.warmup, prof_steps, refine=mixed,
-                                            resync=args.resync)
-    ips = args.steps / wall
-    log(f"{args.precision}: {ips:.3f} iters/s ({1e3 * wall / args.steps:.2f} ms/iter)")
-    pure = None
+    prof_steps = 10
+    mixed = args.precision == "bf16x3"
+    R = args.resync if mixed else 1  # line searches per step
+    side = max(2, args.steps // 4)   # steps of the flavours timed beside the headline
+    log(f"timing {args.precision}: warmup {args.warmup}, steps {args.steps} x {R} line searches")
+    wall, setup_s, stages, resyncs = time_iterations(
+        OMM, torch, dev, s, args.precision, args.steps, args.warmup, prof_steps, refine=mixed,
+        resync=args.resync, per_step=R)
+    ips = args.steps * R / wall
+    log(f"{args.precision}: {ips:.3f} iters/s ({1e3 * wall / (args.steps * R):.3f} ms/line search,"
+        f" {resyncs} resynchronizations in the window)")
+    rates = {}
     if mixed:
-        wp, _, stp = time_iterations(OMM, torch, dev, s, args.precision, args.steps, 2, 0)
-        pure = args.steps / wp
-        log(f"{args.precision} with FP32 state, no resync: {pure:.3f} iters/s")
+        wp, _, _, _ = time_iterations(OMM, torch, dev, s, "bf16x3", 80, 2, 0)
+        rates["bf16_fp32_state_no_resync_iters_per_s"] = 80 / wp
+        log(f"bf16 products with an FP32 state, no resync: {rates['bf16_fp32_state_no_resync_iters_per_s']:.3f} iters/s")
+    if args.precision != "fp32":
+        w32, _, st32, _ = time_iterations(OMM, torch, dev, s, "fp32", 40, 2, 3)
+        rates["fp32_iters_per_s"] = 40 / w32
+        rates["fp32_stages_ms"] = st32
+        log(f"fp32 products: {rates['fp32_iters_per_s']:.3f} iters/s")
 
     fp64 = None
     if not args.no_fp64 and args.precision != "fp64":
         log("timing fp64")
-        w64, _, st64 = time_iterations(OMM, torch, dev, s, "fp64", max(3, args.steps // 4), 1, 3)
-        fp64 = {"iters_per_s": max(3, args.steps // 4) / w64, "stages_ms": st64}
+        w64, _, st64, _ = time_iterations(OMM, torch, dev, s, "fp64", 20, 1, 3)
+        fp64 = {"iters_per_s": 20 / w64, "stages_ms": st64}
         log(f"fp64: {fp64['iters_per_s']:.3f} iters/s")
 
     chol = None
     if not args.no_cholesky and mixed:
         log(f"timing the Cholesky-reduced flavour ({args.precision})")
-        wc, setup_c, stc = time_iterations(OMM, torch, dev, s, args.precision, args.steps,
-                                           args.warmup, prof_steps, refine=True,
-                                           resync=args.resync, flavour="cholesky")
-        chol = {"iters_per_s": args.steps / wc, "setup_s": setup_c, "stages_ms": stc,
+        wc, setup_c, stc, _ = time_iterations(OMM, torch, dev, s, args.precision, side, 1,
+                                              prof_steps, refine=True, resync=args.resync,
+                                              flavour="cholesky", per_step=R)
+        chol = {"iters_per_s": side * R / wc, "setup_s": setup_c, "stages_ms": stc,
+                "steps": side, "line_searches_per_step": R,
                 "note": "Cholesky-reduced flavour: S = L L^T once, no S or P products per line "
                         "search; its iterates are those of P = S^-1 (tau = inf), not of tau = "
                         f"{s.tau}"}
         log(f"cholesky: {chol['iters_per_s']:.3f} iters/s, setup {setup_c:.2f} s")
 
     sparse = None
-    if not args.no_sparse and args.precision == "bf16x3":
+    if not args.no_sparse and mixed:
         log("timing block-sparse operator products (bf16x3)")
-        wsp, _, stsp = time_iterations(OMM, torch, dev, s, args.precision, args.steps, args.warmup,
-                                       prof_steps, refine=True, resync=args.resync, sparse=True)
-        sparse = {"iters_per_s": args.steps / wsp, "stages_ms": stsp,
+        wsp, _, stsp, _ = time_iterations(OMM, torch, dev, s, args.precision, side, 1, prof_steps,
+                                          refine=True, resync=args.resync, sparse=True, per_step=R)
+        sparse = {"iters_per_s": side * R / wsp, "stages_ms": stsp, "steps": side,
+                  "line_searches_per_step": R,
                   "note": "[HD|SD] over the non-zero 32-deep K blocks of each 256-column tile of Hs "
                           "and S only; same iterates as the dense products (bitwise, same tile)"}
         log(f"sparse products: {sparse['iters_per_s']:.3f} iters/s")
@@ -414,7 +521,7 @@ def main():
                 "frac": achieved / peak, "traffic": measured_traffic(args.workload, args.precision),
                 "kernel": f"[HD|SD] = D [Hs|S] ({args.precision}), {op_ms:.3f} ms/launch, "
                           f"{op_flops:.4g} algorithmic flops/launch"}
-    if args.precision == "bf16x3":
+    if mixed:
         # the search direction is bf16-exact, so each product is two bf16 MFMA passes
         # (D_hi B_lo + D_hi B_hi): MFMA work is twice the algorithmic flops
         roofline["hardware_frac"] = 2 * achieved / peak
@@ -422,19 +529,24 @@ def main():
     result = {
         "metric": METRIC, "value": ips, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if mixed else args.precision,
+        "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "N": s.N, "M": s.M, "eta": s.eta,
                    "tau": s.tau, "seed": 0, "c0_seed": 1},
+        "line_searches_per_step": R, "line_searches_timed": args.steps * R,
         "algorithmic_tflops": flops * ips / 1e12,
-        "scheme": (f"{args.precision} MFMA products, FP64 CG state and reductions, FP64 "
-                   f"resynchronization every {args.resync} line searches" if mixed else
-                   "FP64 MFMA products and FP64 reductions"),
+        "scheme": ("bf16 MFMA products with FP32 accumulation (3 passes for the gradient, 2 for "
+                   "every product with the bf16-rounded direction D~, 1 for PG = G~ P~), FP64 CG "
+                   "state, FP64 reductions and line search, FP64 recomputation of the state from "
+                   f"C every {args.resync} line searches (one per step)" if mixed else
+                   f"{args.precision} MFMA products and FP64 reductions"),
         "setup_s": setup_s,
         "stages_ms": stages,
         "roofline": roofline,
     }
-    if pure:
-        result["fp32_state_no_resync_iters_per_s"] = pure
+    if mixed:
+        result["resyncs_in_window"] = resyncs
+    result.update(rates)
     if chol:
         result["cholesky_flavour"] = chol
     if sparse:
@@ -453,12 +565,12 @@ def main():
             log("time to converged: fp64 (1e-8)")
             conv["fp64_1e-8"] = time_to_converged(OMM, torch, dev, s, "fp64", E_ref, 1e-8,
                                                   args.max_iter, args.resync)
-            if args.precision != "fp64":
+            if mixed:
                 log(f"time to converged: {args.precision} with FP64 state (1e-8)")
-                conv[args.precision + "_1e-8"] = time_to_converged(
+                conv["bf16_1e-8"] = time_to_converged(
                     OMM, torch, dev, s, args.precision, E_ref, 1e-8, args.max_iter, args.resync)
                 a = conv["fp64_1e-8"].get("time_to_target_s")
-                b = conv[args.precision + "_1e-8"].get("time_to_target_s")
+                b = conv["bf16_1e-8"].get("time_to_target_s")
                 if a and b:
                     conv["mixed_speedup_1e-8"] = a / b
                 if sparse:
@@ -474,12 +586,27 @@ def main():
             conv["E_ref"] = E_ref
             result["time_to_converged"] = conv
 
+    if args.workload == "c3":
+        log("c1 latency: fp64 line searches on the 128-orbital workload")
+        c1 = config_system("c1", 0)
+        C01 = start_coefficients(c1.S, c1.M, 1)
+        d1 = {k: torch.from_numpy(v).cuda() for k, v in (("H", c1.H), ("S", c1.S), ("T", c1.T),
+                                                          ("C0", C01))}
+        wl, _, _, _ = time_iterations(OMM, torch, d1, c1, "fp64", 100, 20, 0)
+        result["c1_fp64_us_per_iter"] = 1e6 * wl / 100
+        result["c1_workload"] = WORKLOADS["c1"]
+        log(f"c1 fp64: {result['c1_fp64_us_per_iter']:.1f} us per line search")
+
     if not args.no_complex and args.workload == "c3":
         result["complex_kpoints"] = complex_bench(args, torch)
 
+    if not args.no_batched and args.workload == "c3":
+        result["batched"] = batched_bench(args)
+
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: {args.cpu_iters} oracle iterations")
-        result["cpu_baseline"] = cpu_baseline(s, C0, args.cpu_iters)
+        log(f"cpu baseline: {args.cpu_warmup} + {args.cpu_iters} oracle line searches")
+        result["cpu_baseline"] = cpu_baseline(s, C0, args.cpu_iters, args.cpu_warmup,
+                                              closed_form=args.cpu_closed_form)
     print(json.dumps(result), flush=True)
 
 

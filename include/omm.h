@@ -52,7 +52,13 @@ enum {
 enum {
   OMM_FP64 = 0,   /* FP64 MFMA, FP64 storage */
   OMM_FP32 = 1,   /* FP32 MFMA, FP32 storage of the M x N and N x N operands */
-  OMM_BF16X3 = 2  /* BF16 MFMA on hi/lo splits (3 products), FP32 accumulation and storage */
+  OMM_BF16X3 = 2  /* BF16 MFMA on bf16 hi/lo splits with FP32 accumulation: operands with two
+                     planes (x = hi + lo) give products exact to ~2^-17 relative per term.
+                     MFMA passes per product: the gradient 3 (lo*hi + hi*lo + hi*hi); every
+                     product with the search direction 2 (D is rounded to bf16 when it is
+                     formed, so its lo plane is zero); the preconditioning PG = G~ P~ 1 (both
+                     G and P applied as their bf16 roundings; OMM_PG_SPLIT=1 in the environment
+                     makes it 2, with G split hi/lo) */
 };
 
 typedef struct omm_ctx omm_ctx;
@@ -64,9 +70,10 @@ int omm_destroy(omm_ctx *ctx);
 
 /* Select the arithmetic of the products (OMM_FP64 default). fp64_refine != 0 with a mixed mode:
  *  - OMM_BF16X3: the CG state (C, HC, SC, HW, SW) is kept in FP64 while every cubic product runs
- *    in BF16x3; every omm_set_resync() line searches HC, SC, HW, SW and the energy are recomputed
- *    exactly in FP64 from C, and the stopping rule (Eq. 18) is applied to consecutive exact
- *    energies (scaled by the number of line searches between them);
+ *    on bf16 planes; every omm_set_resync() line searches HC, SC, HW, SW and the energy are
+ *    recomputed exactly in FP64 from C, and the stopping rule (Eq. 18) is applied to consecutive
+ *    exact energies (scaled by the number of line searches between them); omm_minimize ends
+ *    with a resynchronization, so its final energy and state are FP64-exact functions of C;
  *  - OMM_FP32: an FP32 minimization to omm_set_mixed_tol() followed by an FP64 one from its C.
  * fp64_refine == 0: the whole minimization runs in the mixed arithmetic with FP32 storage. */
 int omm_set_precision(omm_ctx *ctx, int mode, int fp64_refine);
@@ -131,7 +138,12 @@ int omm_minimize_device(omm_ctx *ctx, const double *dC0, double eta, double tau,
 
 /* Continue the CG of the last minimization (same precision phase, same direction history) for
  * up to `count` more line searches, stopping early when Eq. 18 holds for `tol` (tol = 0 never
- * stops early). No setup work is repeated. Returns OMM_OK (converged), OMM_W_MAXITER (count
+ * stops early). No setup work is repeated. In OMM_BF16X3 + refinement the FP64
+ * resynchronizations stay on the schedule of omm_set_resync() counted across calls (every
+ * `every` line searches since the last one, which omm_minimize's end also performs): a call
+ * that stops between two leaves the incrementally updated FP64 state, whose energy (omm_energy,
+ * the trace) carries the products' rounding since the last resynchronization, and the stopping
+ * rule is only tested at resynchronizations. Returns OMM_OK (converged), OMM_W_MAXITER (count
  * line searches done) or an error; OMM_E_STATE if no minimization is active (new H/S invalidate
  * it). */
 int omm_iterate(omm_ctx *ctx, int count, double tol);
@@ -208,16 +220,26 @@ const char *omm_last_error(const omm_ctx *ctx);
 
 /* ---- many independent systems of uneven size in one set of launches ----
  * Every CG stage is one grouped launch over the tiles of all live systems; converged systems
- * drop out of the tile lists. FP32 MFMA products, FP64 reductions. */
+ * drop out of the tile lists. FP32 (default) or FP64 MFMA products, FP64 reductions. */
 typedef struct omm_batch omm_batch;
 
 int omm_batch_create(int nsys, const int64_t *N, const int64_t *M, omm_batch **out);
 int omm_batch_destroy(omm_batch *b);
+/* Arithmetic of the batched minimization: OMM_FP32 (default: FP32 products and M x N state) or
+ * OMM_FP64; any other mode is OMM_E_ARG. fp64_refine != 0 with OMM_FP32: each system first
+ * runs the FP32 phase to the tolerance of omm_batch_set_mixed_tol() (default 1e-9; the larger
+ * of it and the call's tol), then an FP64 phase from that C to the call's tol, also in grouped
+ * launches; energies, C and the stopping rule then come from the FP64 phase. */
+int omm_batch_set_precision(omm_batch *b, int mode, int fp64_refine);
+int omm_batch_set_mixed_tol(omm_batch *b, double tol);
+/* Line searches of the last omm_batch_minimize per system (nsys entries each, either pointer
+ * nullable): in the FP32 phase and in the FP64 phase. */
+int omm_batch_phase_iterations(omm_batch *b, int *iters32, int *iters64);
 /* System i: host H, S, T (N_i*N_i each; T nullable as for omm_set_HS). */
 int omm_batch_set_HS(omm_batch *b, int i, const double *H, const double *S, const double *T);
 /* C0[i]: host M_i*N_i start of system i (NULL entry: resume from its current C). eta, tau:
- * arrays of nsys values. Returns OMM_OK if every system converged, OMM_W_MAXITER if some did
- * not, or the first error. */
+ * arrays of nsys values; max_iter bounds each phase. Returns OMM_OK if every system converged,
+ * OMM_W_MAXITER if some did not, or the first error. */
 int omm_batch_minimize(omm_batch *b, const double *const *C0, const double *eta,
                        const double *tau, double tol, int max_iter);
 int omm_batch_energy(omm_batch *b, double *E /* nsys */);

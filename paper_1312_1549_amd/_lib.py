@@ -64,6 +64,9 @@ PROTOTYPES = {
     "omm_batch_iterations": (ct.c_int, [_vp, _c_int_p]),
     "omm_batch_get_C": (ct.c_int, [_vp, ct.c_int, _vp]),
     "omm_batch_last_error": (ct.c_char_p, [_vp]),
+    "omm_batch_set_precision": (ct.c_int, [_vp, ct.c_int, ct.c_int]),
+    "omm_batch_set_mixed_tol": (ct.c_int, [_vp, ct.c_double]),
+    "omm_batch_phase_iterations": (ct.c_int, [_vp, _c_int_p, _c_int_p]),
 }
 
 _lib = None

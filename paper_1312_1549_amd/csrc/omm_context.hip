@@ -120,6 +120,7 @@ struct omm_ctx {
   int resync_every = 80;      // line searches between FP64 resynchronizations
   int since_resync = 0;
   double resync_E = 0.0;      // FP64 energy at the last resynchronization
+  double p_residual = -1.0;   // probe residual of the last preconditioner inverse
   std::vector<int> ck_iter;   // FP64-exact energies of the mixed scheme: (line search, E)
   std::vector<double> ck_E;
   int phase_k = 0;            // line searches launched in the active phase
@@ -593,14 +594,26 @@ int prepare_precon(omm_ctx* c, double tau) {
       TRY(dalloc(c, &c->P, nn));
       if (kind == 1) HIPCHK(c, copy_f64(c->S, c->P, (int64_t)nn, c->stream));
       else HIPCHK(c, axpby_f64(c->S, c->T, c->P, 1.0, 1.0 / tau, (int64_t)nn, c->stream));
-      TRY(dalloc(c, &c->inv_work, invert_work_doubles(c->N)));
+      TRY(dalloc(c, &c->inv_work, std::max(invert_work_doubles(c->N),
+                                            inverse_residual_work_doubles(c->N))));
       int bad = 0;
       HIPCHK(c, invert_in_place(c->P, c->N, c->inv_work, c->stream, &bad));
       if (bad) {
         c->p_kind = -1;
-        return fail(c, OMM_E_PRECON, "preconditioner inversion hit a zero or non-finite pivot");
+        return fail(c, OMM_E_PRECON, "preconditioner inversion hit a singular pivot block or a "
+                                     "non-finite value");
       }
       HIPCHK(c, symmetrize(c->P, c->N, c->stream));
+      // the inverse is used only if it inverts: max |X P (S + T/tau) - X| on +-1 probe rows
+      double res = 0.0;
+      HIPCHK(c, inverse_residual(c->P, c->S, kind == 2 ? c->T : nullptr, 1.0 / tau, c->N,
+                                 c->inv_work, c->stream, &res));
+      c->p_residual = res;
+      if (!(res <= INVERSE_RESIDUAL_LIMIT)) {
+        c->p_kind = -1;
+        return fail(c, OMM_E_PRECON, "preconditioner inverse is inaccurate (probe residual " +
+                                         std::to_string(res) + "): S + T/tau is near singular");
+      }
     }
     c->p_kind = kind;
     c->p_tau = tau;
@@ -785,6 +798,11 @@ bool fuse_enabled() {
   return !(e && e[0] == '0');
 }
 
+bool pg_split_enabled() {
+  const char* e = getenv("OMM_PG_SPLIT");
+  return e && e[0] == '1';
+}
+
 // One line search (the stage sequence in the header comment of this file). In BF16x3 mode every
 // GEMM operand is split into bf16 hi/lo planes once, right after it is produced.
 template <typename T>
@@ -825,22 +843,27 @@ int line_search_iteration(omm_ctx* c, Work<T>& w, int compute, const T* Hs, cons
     op.B[1] = b2.p; op.Blo[1] = b2.lo; op.ldb[1] = b2.ld;
     op.K[1] = M;
     // G's bf16 plane for the preconditioner product, from the epilogue (the product takes G
-    // rounded to bf16: no lo plane)
+    // rounded to bf16: no lo plane, unless OMM_PG_SPLIT=1)
     if (fuse && c->p_kind > 0) {
       out_planes(op, c->G_p);
-      op.Clo = nullptr;
+      if (!pg_split_enabled()) op.Clo = nullptr;
     }
     TRY(gemm(c, d, &op, 1, done));
     TRY(fill_pairs(c, Gout, tg, N, N, fuse && c->p_kind > 0 ? &c->G_p : nullptr));
   }
   TRY(prof_mark(c));
-  // BF16x3: the preconditioner is applied as its bf16 rounding (the hi plane of P, a symmetric
-  // matrix of its own) to the bf16 rounding of G, a single MFMA product, and the search direction
-  // is rounded to bf16 when it is formed, so every product with D takes two MFMA products
-  // instead of three (same accuracy: the rounded operand is exact). PG only shapes the search
-  // direction (the line search is exact along whatever D results), and a relative error of
-  // 2^-9 in it stays relative as G shrinks.
-  const int cP = bf ? CBF16X1 : compute, cD = bf ? CBF16X2A : compute;
+  // BF16x3: the preconditioner is applied as its bf16 rounding P~ (the hi plane of P, a symmetric
+  // matrix of its own) to the bf16 rounding G~ of G, a single MFMA product, and the search
+  // direction is rounded to bf16 when it is formed, so every product with D takes two MFMA
+  // products instead of three (same accuracy: the rounded operand is exact). PG only shapes the
+  // search direction; the line search is exact along whatever D results. Each element of G~ is
+  // within 2^-9 of G's, but PG = G~ P~ sums N terms: its error is bounded by ~2^-9 |G| |P|
+  // per element, not relative to PG, which can be much smaller under cancellation, and the
+  // rounding of G makes the applied preconditioner vary from one line search to the next.
+  // OMM_PG_SPLIT=1 applies P~ to G's hi/lo planes instead (two MFMA products, G exact to
+  // ~2^-17).
+  const bool pg_split = bf && pg_split_enabled();
+  const int cP = bf ? (pg_split ? CBF16X2B : CBF16X1) : compute, cD = bf ? CBF16X2A : compute;
   T* PG = G;
   if (c->p_kind > 0) {
     if (bf && !fuse) {
@@ -1109,8 +1132,10 @@ int resync_fp64(omm_ctx* c) {
 
 // Up to `count` line searches of the mixed scheme: BF16x3 products, FP64 state, an FP64
 // resynchronization every `resync_every` line searches. The stopping rule (Eq. 18) is applied
-// to consecutive FP64-exact energies, scaled by the number of line searches between them.
-int mixed64_iterate(omm_ctx* c, double tol, int count, int* done_out) {
+// to consecutive FP64-exact energies, scaled by the number of line searches between them. The
+// schedule counts line searches since the last resynchronization across calls; `close` adds
+// one at the end of the call when the last line search did not fall on the schedule.
+int mixed64_iterate(omm_ctx* c, double tol, int count, bool close, int* done_out) {
   const int K = c->resync_every > 0 ? c->resync_every : 20;
   const double* P = c->p_kind > 0 ? c->P : nullptr;
   int left = count;
@@ -1125,7 +1150,7 @@ int mixed64_iterate(omm_ctx* c, double tol, int count, int* done_out) {
       *done_out = d;
       return OMM_OK;
     }
-    if (c->since_resync >= K || left == 0) {
+    if (c->since_resync >= K || (left == 0 && close)) {
       const int span = c->since_resync;
       const double E_old = c->resync_E;
       TRY(resync_fp64(c));
@@ -1213,7 +1238,7 @@ int minimize_impl(omm_ctx* c, const double* C0, bool C0_device, double eta, doub
     c->resync_E = c->st_host->E;
     c->ck_iter.push_back(0);
     c->ck_E.push_back(c->st_host->E);
-    TRY(mixed64_iterate(c, tol, max_iter, &done1));
+    TRY(mixed64_iterate(c, tol, max_iter, true, &done1));
     c->c_prec = OMM_FP64;
     c->iters = c->st_host->iter;
     c->trace_n = c->iters + 1;
@@ -1725,7 +1750,7 @@ int omm_iterate(omm_ctx* c, int count, double tol) {
   if (!c->phase_active) return fail(c, OMM_E_STATE, "no active minimization to continue");
   int done = 0;
   if (c->phase_mixed64) {
-    TRY(mixed64_iterate(c, tol, count, &done));
+    TRY(mixed64_iterate(c, tol, count, false, &done));
     c->c_prec = OMM_FP64;
   } else if (c->phase_prec == OMM_FP64) {
     TRY(phase_iterate<double>(c, c->w64, CF64, c->Hs, c->S, c->p_kind > 0 ? c->P : nullptr, tol,

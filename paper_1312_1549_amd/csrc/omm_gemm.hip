@@ -12,6 +12,7 @@ gemm_fn pick_bf16x2(const GemmDesc& d);
 sk_fn pick_sk_bf16x3(const GemmDesc& d);
 sk_fn pick_sk_bf16x2(const GemmDesc& d);
 grouped_fn pick_grouped_f32(const GemmDesc& d);
+grouped_fn pick_grouped_f64(const GemmDesc& d);
 
 namespace {
 template <typename TC, typename TX>
@@ -116,8 +117,9 @@ bool gemm_supported(const GemmDesc& d) {
 
 hipError_t gemm_grouped_launch(const GemmDesc& d, const GemmOp* d_ops, const int* d_tile_start,
                                const int* const* d_done, int nops, int grid, hipStream_t s) {
-  if (d.compute != CF32 || nops < 1 || grid < 1) return hipErrorInvalidValue;
-  grouped_fn fn = pick_grouped_f32(d);
+  if ((d.compute != CF32 && d.compute != CF64) || nops < 1 || grid < 1)
+    return hipErrorInvalidValue;
+  grouped_fn fn = d.compute == CF64 ? pick_grouped_f64(d) : pick_grouped_f32(d);
   if (!fn) return hipErrorInvalidValue;
   GroupedArgs g{d_ops, d_tile_start, d_done, nops};
   hipLaunchKernelGGL(fn, dim3(grid), dim3(tile_threads(d.tile, d.compute)), 0, s, g);

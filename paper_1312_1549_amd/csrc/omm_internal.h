@@ -103,9 +103,9 @@ int gemm_grouped_num_tiles();
 bool gemm_supported(const GemmDesc& d);
 int gemm_tile_rows(int tile, int mode);
 int gemm_tile_cols(int tile, int mode);
-// Grouped FP32 products of uneven shapes in one persistent launch of `grid` workgroups. All
-// arrays are device memory: nops ops, tile prefix sums (nops + 1, computed with the tile shape of
-// d.tile), per-op done flags (entries nullable). No split-K.
+// Grouped FP32 or FP64 products of uneven shapes in one persistent launch of `grid` workgroups.
+// All arrays are device memory: nops ops, tile prefix sums (nops + 1, computed with the tile
+// shape of d.tile), per-op done flags (entries nullable). No split-K.
 hipError_t gemm_grouped_launch(const GemmDesc& d, const GemmOp* d_ops, const int* d_tile_start,
                                const int* const* d_done, int nops, int grid, hipStream_t s);
 
@@ -190,14 +190,15 @@ hipError_t scale_f64(double* a, double c, int64_t n, hipStream_t s);
 
 // ---- grouped (batched) stages: one launch over many systems, blockIdx.y = system ----
 struct SysDev {
-  float *C, *HC, *SC, *G0, *G1, *PG, *D, *HD, *SD;  // M x N (FP32)
-  double *HW, *SW, *H1, *S1, *H2, *S2;              // M x M (FP64)
-  double* partials;                                 // GROUP_BLOCKS x NCOEF
+  void *C, *HC, *SC, *G0, *G1, *PG, *D, *HD, *SD;  // M x N, FP32 (f64 = 0) or FP64 (f64 = 1)
+  double *HW, *SW, *H1, *S1, *H2, *S2;             // M x M (FP64)
+  double* partials;                                // GROUP_BLOCKS x NCOEF
   DevState* st;
-  double* trace;                                    // max_iter + 2 entries
+  double* trace;                                   // max_iter + 2 entries
   int M, N;
-  int precon;                                       // PG holds G P (else PG aliases G)
+  int precon;                                      // PG holds G P (else PG aliases G)
   int paired;  // real embedding of a complex system: products computed for the first M / 2 rows
+  int f64;     // type of the M x N arrays
 };
 constexpr int GROUP_BLOCKS = 64;
 
@@ -217,6 +218,13 @@ hipError_t group_pair_rows(const SysDev* d_sys, int nsys, int which, int parity,
 // sets *bad (host) to 1 if a pivot block was singular or a non-finite value appeared.
 hipError_t invert_in_place(double* A, int64_t n, double* work, hipStream_t s, int* bad);
 size_t invert_work_doubles(int64_t n);
+// max_ij |(X P A - X)_ij| over 16 probe rows X of +-1 entries, A = S + inv_tau T (T nullable:
+// A = S), written to *res (host) after a stream synchronization. P, S, T symmetric, n x n.
+hipError_t inverse_residual(const double* P, const double* S, const double* T, double inv_tau,
+                            int64_t n, double* work, hipStream_t s, double* res);
+size_t inverse_residual_work_doubles(int64_t n);
+// An inverse whose probe residual exceeds this is rejected (OMM_E_PRECON).
+constexpr double INVERSE_RESIDUAL_LIMIT = 1e-8;
 // Cholesky factorization S = L L^T in place (L lower, strict upper set to zero); *bad != 0 when
 // a pivot is not positive (S not positive definite) or the result is not finite.
 hipError_t cholesky_in_place(double* A, int64_t n, double* work, hipStream_t s, int* bad);

@@ -960,22 +960,33 @@ __global__ void g_energy_init_final(const SysDev* sys) {
   const SysDev& d = sys[blockIdx.y];
   f_energy_init_final(d.partials, GROUP_BLOCKS, d.st, d.trace);
 }
+template <typename T>
+__device__ __forceinline__ void g_pr_partials_t(const SysDev& d, int parity, int first) {
+  const T* G = static_cast<const T*>(parity ? d.G1 : d.G0);
+  const T* Gp = static_cast<const T*>(parity ? d.G0 : d.G1);
+  const T* PG = d.precon ? static_cast<const T*>(d.PG) : G;
+  b_pr_partials<T>(G, PG, Gp, (int64_t)d.M * d.N, first, d.partials, d.st, blockIdx.x, gridDim.x);
+}
 __global__ void g_pr_partials(const SysDev* sys, int parity, int first) {
   const SysDev& d = sys[blockIdx.y];
-  const float* G = parity ? d.G1 : d.G0;
-  const float* Gp = parity ? d.G0 : d.G1;
-  b_pr_partials<float>(G, d.precon ? d.PG : G, Gp, (int64_t)d.M * d.N, first, d.partials, d.st,
-                       blockIdx.x, gridDim.x);
+  if (d.f64) g_pr_partials_t<double>(d, parity, first);
+  else g_pr_partials_t<float>(d, parity, first);
 }
 __global__ void g_pr_final(const SysDev* sys, int first) {
   const SysDev& d = sys[blockIdx.y];
   f_pr_final(d.partials, GROUP_BLOCKS, first, d.st);
 }
+template <typename T>
+__device__ __forceinline__ void g_direction_t(const SysDev& d, int parity, int first) {
+  const T* G = static_cast<const T*>(parity ? d.G1 : d.G0);
+  const T* PG = d.precon ? static_cast<const T*>(d.PG) : G;
+  b_direction<T>(PG, static_cast<T*>(d.D), (int64_t)d.M * d.N, first, d.st, blockIdx.x,
+                 gridDim.x);
+}
 __global__ void g_direction(const SysDev* sys, int parity, int first) {
   const SysDev& d = sys[blockIdx.y];
-  const float* G = parity ? d.G1 : d.G0;
-  b_direction<float>(d.precon ? d.PG : G, d.D, (int64_t)d.M * d.N, first, d.st, blockIdx.x,
-                     gridDim.x);
+  if (d.f64) g_direction_t<double>(d, parity, first);
+  else g_direction_t<float>(d, parity, first);
 }
 __global__ void g_coef_partials(const SysDev* sys) {
   const SysDev& d = sys[blockIdx.y];
@@ -985,10 +996,16 @@ __global__ void g_line_final(const SysDev* sys) {
   const SysDev& d = sys[blockIdx.y];
   f_line_final(d.partials, GROUP_BLOCKS, d.st);
 }
+template <typename T>
+__device__ __forceinline__ void g_update_mn_t(const SysDev& d) {
+  b_update_mn<T>(static_cast<T*>(d.C), static_cast<const T*>(d.D), static_cast<T*>(d.HC),
+                 static_cast<const T*>(d.HD), static_cast<T*>(d.SC), static_cast<const T*>(d.SD),
+                 (int64_t)d.M * d.N, d.st, blockIdx.x, gridDim.x);
+}
 __global__ void g_update_mn(const SysDev* sys) {
   const SysDev& d = sys[blockIdx.y];
-  b_update_mn<float>(d.C, d.D, d.HC, d.HD, d.SC, d.SD, (int64_t)d.M * d.N, d.st, blockIdx.x,
-                     gridDim.x);
+  if (d.f64) g_update_mn_t<double>(d);
+  else g_update_mn_t<float>(d);
 }
 template <typename T>
 __device__ __forceinline__ void pair_fill(T* X, int rh, int h, int64_t r, int64_t c) {
@@ -1002,21 +1019,24 @@ __global__ void g_pair_rows(const SysDev* sys, int which, int parity, int check_
   if (!d.paired || (check_done && d.st->done)) return;
   if (which == 3 && !d.precon) return;  // PG aliases G
   const int rh = d.M / 2;
-  const bool mm = which == 1 || which == 5;  // M x M (FP64) or M x N (FP32)
+  const bool mm = which == 1 || which == 5;  // M x M (FP64) or M x N (FP32 or FP64 state)
   const int h = (mm ? d.M : d.N) / 2;
-  float* xf[2] = {nullptr, nullptr};
+  void* xs[2] = {nullptr, nullptr};  // M x N arrays of the state's type
   double* xd[4] = {nullptr, nullptr, nullptr, nullptr};
-  if (which == 0) { xf[0] = d.HC; xf[1] = d.SC; }
-  if (which == 2) xf[0] = parity ? d.G1 : d.G0;
-  if (which == 3) xf[0] = d.PG;
-  if (which == 4) { xf[0] = d.HD; xf[1] = d.SD; }
+  if (which == 0) { xs[0] = d.HC; xs[1] = d.SC; }
+  if (which == 2) xs[0] = parity ? d.G1 : d.G0;
+  if (which == 3) xs[0] = d.PG;
+  if (which == 4) { xs[0] = d.HD; xs[1] = d.SD; }
   if (which == 1) { xd[0] = d.HW; xd[1] = d.SW; }
   if (which == 5) { xd[0] = d.H1; xd[1] = d.S1; xd[2] = d.H2; xd[3] = d.S2; }
   for (int64_t r = blockIdx.y; r < rh; r += gridDim.y)
     for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < 2 * (int64_t)h;
          c += (int64_t)gridDim.x * NT) {
-      for (int a = 0; a < 2; ++a)
-        if (xf[a]) pair_fill(xf[a], rh, h, r, c);
+      for (int a = 0; a < 2; ++a) {
+        if (!xs[a]) continue;
+        if (d.f64) pair_fill(static_cast<double*>(xs[a]), rh, h, r, c);
+        else pair_fill(static_cast<float*>(xs[a]), rh, h, r, c);
+      }
       for (int a = 0; a < 4; ++a)
         if (xd[a]) pair_fill(xd[a], rh, h, r, c);
     }

@@ -1,17 +1,21 @@
 // One-time FP64 inversion for the preconditioner P = (S + T/tau)^-1 (Sec. 2.4, Eq. 17): an
 // in-place blocked Gauss-Jordan sweep. The paper inverts once per MD step with a library
-// LU; here each block column costs one tiny pivot-block inversion plus two MFMA GEMMs, so the
-// 2 n^3 flops run on matrix cores.
+// LU, since P need not be positive definite (Sec. 3.1); here each block column costs one
+// pivot-block inversion plus two MFMA GEMMs, so the 2 n^3 flops run on matrix cores.
 //
 // Step for pivot block K (width b), with A the current matrix:
 //   U  = A[:, K] with its diagonal block replaced by A_KK - I      (column panel copy)
-//   W  = A_KK^-1                                                    (one workgroup)
+//   W  = A_KK^-1                                                    (one workgroup, in LDS)
 //   A[:, K] = e_K  (zero column panel, identity diagonal block)
 //   R  = W A[K, :]                                                  (b x n GEMM)
 //   A -= U R                                                        (rank-b GEMM update)
 // which leaves A[K,K] = W, A[K,J] = W A_KJ, A[I,K] = -A_IK W and the Schur update elsewhere;
-// after the last block A holds the inverse. No pivoting: S + T/tau is symmetric positive
-// definite for the workloads here. A zero or non-finite pivot is reported, never hidden.
+// after the last block A holds the inverse. The pivot block is inverted by Gauss-Jordan with
+// partial (row) pivoting inside the block, so an indefinite S + T/tau whose diagonal entries
+// vanish or change sign along the sweep is handled as long as each pivot block is
+// nonsingular; the blocks themselves are not exchanged. A singular pivot block or a non-finite
+// value is reported, and inverse_residual() measures ||A P X - X|| on probe vectors so that a
+// caller can reject an inaccurate inverse instead of using it.
 #include <math.h>
 
 #include "omm_internal.h"
@@ -20,6 +24,7 @@ namespace omm {
 namespace {
 
 constexpr int NB = 128;
+constexpr int PROBES = 16;  // probe rows of inverse_residual
 
 // U = A[:, k0:k0+b] (ld b) with U[k0+i][i] -= 1; W = A[k0:k0+b, k0:k0+b]; then
 // A[:, k0:k0+b] = e_K.
@@ -37,33 +42,115 @@ __global__ void k_panel(double* A, int64_t n, int64_t k0, int b, double* U, doub
   }
 }
 
-// In-place Gauss-Jordan inverse of the b x b block W by one workgroup.
+// In-place inverse of the b x b block W (b <= NB) by Gauss-Jordan with partial row pivoting,
+// one workgroup of 1024 threads, the block held in LDS. Step p: the row of largest |W[i][p]|,
+// i >= p, is exchanged with row p (recorded in perm[p]), then the usual in-place elimination
+// with that pivot. Pivoting the rows of W yields (P W)^-1 = W^-1 P^T, so the column exchanges
+// are undone in reverse order at the end. A zero or non-finite pivot sets *bad.
 __global__ __launch_bounds__(1024) void k_small_gj(double* W, int b, int* bad) {
+  __shared__ double a[NB * NB];
   __shared__ double rowp[NB], colp[NB];
-  __shared__ double piv;
+  __shared__ int perm[NB];
+  __shared__ double wv[16];
+  __shared__ int wi[16];
+  __shared__ int piv_row;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < b * b; e += blockDim.x) a[e] = W[e];
+  __syncthreads();
   for (int p = 0; p < b; ++p) {
-    if (threadIdx.x == 0) {
-      const double d = W[p * b + p];
-      if (!(fabs(d) > 0.0) || !isfinite(d)) atomicOr(bad, 1);
-      piv = 1.0 / d;
-    }
-    for (int t = threadIdx.x; t < b; t += blockDim.x) {
-      rowp[t] = W[p * b + t];
-      colp[t] = W[t * b + p];
+    // pivot search over rows p .. b-1 of column p: the first two waves cover 128 rows
+    if (wave < 2) {
+      const int i = p + tid;
+      double v = i < b ? fabs(a[i * b + p]) : -1.0;
+      int r = i;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_down(v, o);
+        const int r2 = __shfl_down(r, o);
+        if (v2 > v || (v2 == v && r2 < r)) {
+          v = v2;
+          r = r2;
+        }
+      }
+      if (lane == 0) {
+        wv[wave] = v;
+        wi[wave] = r;
+      }
     }
     __syncthreads();
-    const double ip = piv;
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+    if (tid == 0) {
+      int r = wi[0];
+      if (wv[1] > wv[0]) r = wi[1];
+      if (r >= b) r = p;
+      piv_row = r;
+      perm[p] = r;
+    }
+    __syncthreads();
+    const int r = piv_row;
+    if (r != p)
+      for (int t = tid; t < b; t += blockDim.x) {
+        const double x = a[p * b + t];
+        a[p * b + t] = a[r * b + t];
+        a[r * b + t] = x;
+      }
+    __syncthreads();
+    const double d = a[p * b + p];
+    if (tid == 0 && (!(fabs(d) > 0.0) || !isfinite(d))) atomicOr(bad, 1);
+    const double ip = 1.0 / d;
+    for (int t = tid; t < b; t += blockDim.x) {
+      rowp[t] = a[p * b + t];
+      colp[t] = a[t * b + p];
+    }
+    __syncthreads();
+    for (int e = tid; e < b * b; e += blockDim.x) {
       const int i = e / b, j = e % b;
       double v;
       if (i == p && j == p) v = ip;
       else if (i == p) v = rowp[j] * ip;
       else if (j == p) v = -colp[i] * ip;
-      else v = W[e] - colp[i] * rowp[j] * ip;
-      W[e] = v;
+      else v = a[e] - colp[i] * rowp[j] * ip;
+      a[e] = v;
     }
     __syncthreads();
   }
+  // undo the row exchanges as column exchanges, last first
+  for (int p = b - 1; p >= 0; --p) {
+    const int r = perm[p];
+    if (r != p)
+      for (int i = tid; i < b; i += blockDim.x) {
+        const double x = a[i * b + p];
+        a[i * b + p] = a[i * b + r];
+        a[i * b + r] = x;
+      }
+    __syncthreads();
+  }
+  for (int e = tid; e < b * b; e += blockDim.x) W[e] = a[e];
+}
+
+// Probe vectors for inverse_residual: X[r][i] = +-1 from an integer hash of (r, i).
+__global__ void k_probe(double* X, int64_t n, int rows) {
+  const int64_t total = n * rows;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    uint64_t h = (uint64_t)e * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    h ^= h >> 31;
+    h *= 0xD6E8FEB86659FD93ull;
+    h ^= h >> 32;
+    X[e] = (h & 1) ? 1.0 : -1.0;
+  }
+}
+
+// *out = max |Z| over `total` elements (one workgroup).
+__global__ __launch_bounds__(1024) void k_maxabs(const double* Z, int64_t total, double* out) {
+  __shared__ double m[1024];
+  double v = 0.0;
+  for (int64_t e = threadIdx.x; e < total; e += 1024) v = fmax(v, fabs(Z[e]));
+  m[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) m[threadIdx.x] = fmax(m[threadIdx.x], m[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = (isfinite(m[0]) ? m[0] : INFINITY);
 }
 
 // Cholesky factorization of the b x b diagonal block at (k0, k0) of A in LDS (lower, right
@@ -186,6 +273,52 @@ hipError_t invert_in_place(double* A, int64_t n, double* work, hipStream_t s, in
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   *bad_host = h;
   return hipSuccess;
+}
+
+size_t inverse_residual_work_doubles(int64_t n) { return (size_t)3 * PROBES * n + 8; }
+
+// max_ij |(X P A)_ij - X_ij| for PROBES rows X of +-1 entries, with A = S + (1/tau) T (T null:
+// A = S): X P A = X exactly when P = A^-1, and the residual of a backward-stable inverse is
+// ~ eps times the growth of the elimination. P, S, T are symmetric, so every product reads
+// its operator k-contiguous.
+hipError_t inverse_residual(const double* P, const double* S, const double* T, double inv_tau,
+                            int64_t n, double* work, hipStream_t s, double* res_host) {
+  double* X = work;
+  double* Y = X + (size_t)PROBES * n;
+  double* Z = Y + (size_t)PROBES * n;
+  double* out = Z + (size_t)PROBES * n;
+  const int64_t total = (int64_t)PROBES * n;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_probe, dim3(blocks), dim3(256), 0, s, X, n, PROBES);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  GemmDesc d{CF64, T_F64, T_F64, T_F64, T_F64, KC, KC, 0, 1};
+  auto op_of = [&](const double* A, const double* B, double* C, const double* Xa, double alpha,
+                   double beta) {
+    GemmOp op{};
+    op.M = PROBES; op.N = (int)n; op.nseg = 1;
+    op.A[0] = A; op.lda[0] = n;
+    op.B[0] = B; op.ldb[0] = n;
+    op.K[0] = (int)n;
+    op.C = C; op.ldc = n;
+    op.X = Xa; op.ldx = Xa ? n : 0;
+    op.alpha = alpha; op.beta = beta;
+    return op;
+  };
+  GemmOp o1 = op_of(X, P, Y, nullptr, 1.0, 0.0);  // Y = X P
+  if ((e = gemm_launch(d, &o1, 1, nullptr, nullptr, 0, s)) != hipSuccess) return e;
+  GemmOp o2 = op_of(Y, S, Z, X, 1.0, -1.0);  // Z = Y S - X
+  if ((e = gemm_launch(d, &o2, 1, nullptr, nullptr, 0, s)) != hipSuccess) return e;
+  if (T) {
+    GemmOp o3 = op_of(Y, T, Z, Z, inv_tau, 1.0);  // Z += (1/tau) Y T
+    if ((e = gemm_launch(d, &o3, 1, nullptr, nullptr, 0, s)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_maxabs, dim3(1), dim3(1024), 0, s, Z, total, out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(res_host, out, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return e;
+  return hipStreamSynchronize(s);
 }
 
 size_t cholesky_work_doubles() { return (size_t)NB * NB + 8; }

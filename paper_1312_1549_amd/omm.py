@@ -299,9 +299,13 @@ class OMMComplex(OMM):
 
 
 class OMMBatch:
-    """Many independent systems of uneven size (FP32 products, FP64 reductions)."""
+    """Many independent systems of uneven size (FP32 or FP64 products, FP64 reductions).
 
-    def __init__(self, Ns: Sequence[int], Ms: Sequence[int]):
+    ``precision="fp32"`` with ``refine=True`` runs an FP64 phase after the FP32 one (both in
+    grouped launches); ``mixed_tol`` is the FP32 phase's stopping threshold."""
+
+    def __init__(self, Ns: Sequence[int], Ms: Sequence[int], precision: str = "fp32",
+                 refine: bool = False, mixed_tol: Optional[float] = None):
         self._L = lib()
         self.Ns = [int(n) for n in Ns]
         self.Ms = [int(m) for m in Ms]
@@ -313,6 +317,22 @@ class OMMBatch:
         if r != OK:
             raise OMMError(r, "omm_batch_create failed")
         self._h = h
+        self.set_precision(precision, refine)
+        if mixed_tol is not None:
+            self._check(self._L.omm_batch_set_mixed_tol(self._h, float(mixed_tol)))
+
+    def set_precision(self, precision: str = "fp32", refine: bool = False):
+        self._check(self._L.omm_batch_set_precision(self._h, PRECISIONS[precision],
+                                                    1 if refine else 0))
+
+    def phase_iterations(self):
+        """(line searches of the FP32 phase, of the FP64 phase) per system."""
+        k = len(self.Ns)
+        a = np.zeros(k, dtype=np.int32)
+        b = np.zeros(k, dtype=np.int32)
+        self._check(self._L.omm_batch_phase_iterations(
+            self._h, a.ctypes.data_as(ct.POINTER(ct.c_int)), b.ctypes.data_as(ct.POINTER(ct.c_int))))
+        return a, b
 
     def _check(self, r: int) -> int:
         if r < 0:
@@ -371,7 +391,8 @@ class OMMBatchComplex(OMMBatch):
     """k-point batch: complex Hermitian systems (complex sizes Ns, Ms) solved together through
     their real embeddings. Inputs are complex NumPy arrays."""
 
-    def __init__(self, Ns: Sequence[int], Ms: Sequence[int]):
+    def __init__(self, Ns: Sequence[int], Ms: Sequence[int], precision: str = "fp32",
+                 refine: bool = False, mixed_tol: Optional[float] = None):
         self._L = lib()
         self.Nc = [int(n) for n in Ns]
         self.Mc = [int(m) for m in Ms]
@@ -384,6 +405,9 @@ class OMMBatchComplex(OMMBatch):
         if r != OK:
             raise OMMError(r, "omm_batch_create_complex failed")
         self._h = h
+        self.set_precision(precision, refine)
+        if mixed_tol is not None:
+            self._check(self._L.omm_batch_set_mixed_tol(self._h, float(mixed_tol)))
 
     def set_HS(self, i: int, H, S, T=None):
         n = (self.Nc[i], self.Nc[i])

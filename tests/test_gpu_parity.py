@@ -144,6 +144,45 @@ def test_fp64_c2_trajectory_and_minimum(lib_ok, c2):
                                atol=1e-11 * np.abs(Pref).max())
 
 
+def test_indefinite_preconditioner_is_inverted(lib_ok, c2):
+    """Sec. 3.1: P need not be positive definite. At tau = 0.1 the kinetic term dominates and
+    S + T/tau of the 2048-orbital lattice has negative eigenvalues (T is indefinite there): the
+    blocked Gauss-Jordan sweep with pivoting inside each pivot block still inverts it (LAPACK's
+    pivoted LU inverse of the oracle to 1e-10), and the first line searches follow the oracle's."""
+    s, C0, w = c2
+    tau = 0.1
+    ev = np.linalg.eigvalsh(s.S + s.T / tau)
+    assert ev[0] < 0 < ev[-1] and np.min(np.abs(ev)) > 1e-3
+    _say(f"indefinite preconditioner c2 N={s.N} tau={tau} ({int(np.sum(ev < 0))} negative eigenvalues)")
+    solver, _ = _run(lib_ok, s, C0, 0.5, tau, 0.0, 3)
+    P = solver.preconditioner()
+    ref = oracle.preconditioner(s.S, s.T, tau)
+    err = np.max(np.abs(P - ref)) / np.max(np.abs(ref))
+    print(f"  max |P - P_ref| / max |P_ref| = {err:.2e}")
+    assert err <= 1e-10
+    tr = solver.energy_trace()
+    ref_run = oracle.minimize(s.H, s.S, s.T, C0, 0.5, tau, 0.0, 3)
+    np.testing.assert_allclose(tr, ref_run.energies, rtol=1e-10, atol=0)
+
+
+def test_singular_preconditioner_is_refused(lib_ok, c2):
+    """tau = -mu for the most negative eigenvalue mu of the pencil (T, S) makes S + T/tau
+    singular (T v = mu S v): the inverse cannot be formed accurately, and the call fails with
+    OMM_E_PRECON instead of running with it."""
+    from paper_1312_1549_amd import OMMError
+
+    s, C0, w = c2
+    mu = brute.generalized_eigh_lapack(s.T, s.S, 1)[0][0]
+    assert mu < 0
+    tau = -float(mu)
+    _say(f"singular preconditioner c2 N={s.N} tau={tau:.6f}")
+    solver = lib_ok(s.N, s.M, precision="fp64")
+    solver.set_HS(s.H, s.S, s.T)
+    with pytest.raises(OMMError) as e:
+        solver.minimize(C0, eta=0.5, tau=tau, tol=0.0, max_iter=2)
+    assert e.value.code == -6
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_mixed_precision_c2(lib_ok, c2, precision):
     s, C0, w = c2
