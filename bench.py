@@ -396,6 +396,24 @@ def batched_bench(args, standalone=False):
     }
 
 
+def summarize_pmc(csv_path, kernel_substr):
+    """Per-dispatch counter values of the kernels whose name contains `kernel_substr`, from a
+    rocprofv3 --pmc counter_collection CSV: one line per counter with the mean and the values."""
+    import csv
+    from collections import defaultdict
+
+    vals = defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if kernel_substr not in r["Kernel_Name"]:
+            continue
+        vals[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = []
+    for k, v in sorted(vals.items()):
+        out.append(f"{k}: dispatches {len(v)}, mean {sum(v) / len(v):.6g}, values "
+                   + ", ".join(f"{x:.6g}" for x in v[:8]))
+    return "\n".join(out)
+
+
 def copy_kernel(nbytes):
     """A plain device copy of a known size (reads and writes `nbytes` each): the calibration
     kernel for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -411,6 +429,9 @@ def copy_kernel(nbytes):
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
         print(summarize_rocprof(sys.argv[2]))
+        return
+    if len(sys.argv) > 3 and sys.argv[1] == "--summarize-pmc":
+        print(summarize_pmc(sys.argv[2], sys.argv[3]))
         return
     if len(sys.argv) > 2 and sys.argv[1] == "--copy-kernel":
         copy_kernel(int(sys.argv[2]))
@@ -435,11 +456,18 @@ def main():
     ap.add_argument("--no-complex", action="store_true",
                     help="skip the complex Hermitian (k-point) rates and time to converged")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batch")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline scheme only (profiling runs): implies every --no-* "
+                         "flag and skips the side rates and the latency workload")
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--resync", type=int, default=80)
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--cpu-warmup", type=int, default=2)
     args = ap.parse_args()
+    if args.only_headline:
+        for flag in ("no_converge", "no_cpu_baseline", "no_fp64", "no_cholesky", "no_sparse",
+                     "no_complex", "no_batched"):
+            setattr(args, flag, True)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -472,11 +500,11 @@ def main():
     log(f"{args.precision}: {ips:.3f} iters/s ({1e3 * wall / (args.steps * R):.3f} ms/line search,"
         f" {resyncs} resynchronizations in the window)")
     rates = {}
-    if mixed:
+    if mixed and not args.only_headline:
         wp, _, _, _ = time_iterations(OMM, torch, dev, s, "bf16x3", 80, 2, 0)
         rates["bf16_fp32_state_no_resync_iters_per_s"] = 80 / wp
         log(f"bf16 products with an FP32 state, no resync: {rates['bf16_fp32_state_no_resync_iters_per_s']:.3f} iters/s")
-    if args.precision != "fp32":
+    if args.precision != "fp32" and not args.only_headline:
         w32, _, st32, _ = time_iterations(OMM, torch, dev, s, "fp32", 40, 2, 3)
         rates["fp32_iters_per_s"] = 40 / w32
         rates["fp32_stages_ms"] = st32
@@ -586,7 +614,7 @@ def main():
             conv["E_ref"] = E_ref
             result["time_to_converged"] = conv
 
-    if args.workload == "c3":
+    if args.workload == "c3" and not args.only_headline:
         log("c1 latency: fp64 line searches on the 128-orbital workload")
         c1 = config_system("c1", 0)
         C01 = start_coefficients(c1.S, c1.M, 1)
