@@ -165,6 +165,16 @@ int omm_edm_device(omm_ctx *ctx, double *d_edm);
  * each, FP64), evaluated at the current C (exact derivatives of the minimum at convergence). */
 int omm_backward_device(omm_ctx *ctx, double gE, double *d_gH, double *d_gS);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * or training loops, harnesses that forbid allocation): omm_backward_device's results (same
+ * arguments, layout and ownership, equal to rounding: the C^T X C sums run over chunks of C's
+ * rows) with no hipMalloc/hipFree and no use of the context's scratch buffers. Its only
+ * scratch is a 16 MiB array in the library's static device memory, one copy per GPU held
+ * until the process ends; calls that overlap on one GPU race on it (serialize them). Limits:
+ * N <= 32768 (N <= 2^21 / min(M, 64)); larger N -> OMM_E_ARG. The Cholesky flavour ->
+ * OMM_E_STATE (use omm_backward_device). */
+int omm_backward_device_noalloc(omm_ctx *ctx, double gE, double *d_gH, double *d_gS);
+
 /* Current C (host M*N), HW and SW (host M*M each; either may be NULL). */
 int omm_get_C(omm_ctx *ctx, double *C);
 int omm_get_subspace(omm_ctx *ctx, double *HW, double *SW);

@@ -48,6 +48,7 @@ PROTOTYPES = {
     "omm_edm": (ct.c_int, [_vp, _vp]),
     "omm_edm_device": (ct.c_int, [_vp, _vp]),
     "omm_backward_device": (ct.c_int, [_vp, ct.c_double, _vp, _vp]),
+    "omm_backward_device_noalloc": (ct.c_int, [_vp, ct.c_double, _vp, _vp]),
     "omm_get_C": (ct.c_int, [_vp, _vp]),
     "omm_get_subspace": (ct.c_int, [_vp, _vp, _vp]),
     "omm_get_preconditioner": (ct.c_int, [_vp, _vp]),

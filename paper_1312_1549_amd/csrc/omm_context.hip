@@ -1796,3 +1796,82 @@ const char* omm_last_error(const omm_ctx* c) {
 }
 
 }  // extern "C"
+
+// ---- the backward pass without allocation ------------------------------------------------------
+// omm_backward_device_noalloc computes what omm_backward_device does through a fixed scratch
+// array instead of the context's buffers or any allocation: rho = 2 C^T (2I - SW) C and
+// EDM = 2 C^T HW C are accumulated over chunks of R rows of C,
+//   Z = 2 C[r0:r1] - SW[r0:r1] C  then  d_gH += 2 gE C[r0:r1]^T Z,
+//   Z = HW[r0:r1] C               then  d_gS -= 2 gE C[r0:r1]^T Z,
+// with Z (R x N) in `scratch`, and finally d_gS -= eta d_gH. R = min(M, capacity / N) must be at
+// least NOALLOC_MIN_ROWS (or M), which bounds N. Every call on a device shares that device's
+// copy of the array: calls that overlap on one GPU race.
+namespace {
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = (int64_t)1 << 21;  // 16 MiB per device
+constexpr int64_t NOALLOC_MIN_ROWS = 64;
+__device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+// The device address of this device's copy of `scratch` (looked up once per device).
+int scratch_address(omm_ctx* c, double** out) {
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(c, OMM_E_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, OMM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return OMM_OK;
+}
+}  // namespace
+
+extern "C" int omm_backward_device_noalloc(omm_ctx* c, double gE, double* d_gH, double* d_gS) {
+  if (!c || !d_gH || !d_gS) return c ? fail(c, OMM_E_ARG, "null output") : OMM_E_ARG;
+  if (d_gH == d_gS) return fail(c, OMM_E_ARG, "d_gH and d_gS must not alias");
+  const int64_t M = c->M, N = c->N;
+  const int64_t R = std::min<int64_t>(M, NOALLOC_SCRATCH_DOUBLES / N);
+  if (R < std::min<int64_t>(M, NOALLOC_MIN_ROWS))
+    return fail(c, OMM_E_ARG, "omm_backward_device_noalloc: N = " + std::to_string(N) +
+                                  " exceeds its scratch (N <= " +
+                                  std::to_string(NOALLOC_SCRATCH_DOUBLES / NOALLOC_MIN_ROWS) +
+                                  "); use omm_backward_device");
+  TRY(need_minimized(c));
+  if (c->c_flavour == OMM_FLAVOUR_CHOLESKY)
+    return fail(c, OMM_E_STATE, "omm_backward_device_noalloc: the Cholesky flavour needs C~ L^-1 "
+                                "in an allocated buffer; use omm_backward_device");
+  TRY(c64(c));  // converts into the context's own FP64 C (no allocation)
+  double* Z = nullptr;
+  TRY(scratch_address(c, &Z));
+  const double* C = c->w64.C;
+  // FP64 tile 0 (128 x 128), no split-K: no workspace
+  const GemmDesc dz{CF64, T_F64, T_F64, T_F64, T_F64, KC, RC, 0, 1};   // Z = X[r0:r1] C
+  const GemmDesc dc{CF64, T_F64, T_F64, T_F64, T_F64, RC, RC, 0, 1};   // out += C[r0:r1]^T Z
+  for (int64_t r0 = 0; r0 < M; r0 += R) {
+    const int rows = (int)std::min<int64_t>(R, M - r0);
+    for (int which = 0; which < 2; ++which) {
+      const double* X = which == 0 ? c->SW : c->HW;
+      double* out = which == 0 ? d_gH : d_gS;
+      // which 0: Z = 2 C[r0:r1] - SW[r0:r1] C;  which 1: Z = HW[r0:r1] C
+      GemmOp oz = make_op(rows, (int)N, (int)M, X + r0 * M, M, C, N, Z, N,
+                          which == 0 ? -1.0 : 1.0, which == 0 ? C + r0 * N : nullptr, N,
+                          which == 0 ? 2.0 : 0.0);
+      HIPCHK(c, gemm_launch(dz, &oz, 1, nullptr, nullptr, 0, c->stream));
+      // out (+)= (+-2 gE) C[r0:r1]^T Z: A(m, k) = C[r0 + k][m], B(k, n) = Z[k][n]
+      const double sc = which == 0 ? 2.0 * gE : -2.0 * gE;
+      GemmOp oc = make_op((int)N, (int)N, rows, C + r0 * N, N, Z, N, out, N, sc,
+                          r0 > 0 ? out : nullptr, N, r0 > 0 ? 1.0 : 0.0);
+      HIPCHK(c, gemm_launch(dc, &oc, 1, nullptr, nullptr, 0, c->stream));
+    }
+  }
+  // dE/dS = -EDM - eta rho: d_gS = gE (-EDM) - eta (gE rho)
+  HIPCHK(c, axpby_f64(d_gS, d_gH, d_gS, 1.0, -c->eta_last, N * N, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return OMM_OK;
+}
