@@ -93,7 +93,8 @@ def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=
     solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # setup only
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    solver.iterate(warmup * per_step)
+    # at least two untimed line searches: the first two of a phase tune every GEMM shape
+    solver.iterate(max(warmup * per_step, 2))
     solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # restart from C0
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -42,88 +42,125 @@ __global__ void k_panel(double* A, int64_t n, int64_t k0, int b, double* U, doub
   }
 }
 
-// In-place inverse of the b x b block W (b <= NB) by Gauss-Jordan with partial row pivoting,
-// one workgroup of 1024 threads, the block held in LDS. Step p: the row of largest |W[i][p]|,
-// i >= p, is exchanged with row p (recorded in perm[p]), then the usual in-place elimination
-// with that pivot. Pivoting the rows of W yields (P W)^-1 = W^-1 P^T, so the column exchanges
-// are undone in reverse order at the end. A zero or non-finite pivot sets *bad.
+// In-place inverse of the b x b block W (b <= NB = 128) by Gauss-Jordan with partial row
+// pivoting, one workgroup of 1024 threads. Thread t holds column j = t % 128 of rows
+// g + 8 k (g = t / 128, k = 0..15) in registers; LDS carries only what a step shares: the
+// pivot candidates, the pivot row and the pivot column. Step p: the row r >= p of largest
+// |W[r][p]| is exchanged with row p (perm[p] = r), then the usual in-place elimination with that
+// pivot. Pivoting the rows yields (P W)^-1 = W^-1 P^T, so the column exchanges are undone in
+// reverse order: column c of the result is the eliminated column src[c]. A zero or non-finite
+// pivot sets *bad.
+constexpr int GJ_RPT = NB / 8;  // rows per thread
+
+// w[k] for a k known only at run time, selected without indexing the register array
+__device__ __forceinline__ double gj_get(const double (&w)[GJ_RPT], int k) {
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < GJ_RPT; ++q) v = q == k ? w[q] : v;
+  return v;
+}
+__device__ __forceinline__ void gj_set(double (&w)[GJ_RPT], int k, double v) {
+#pragma unroll
+  for (int q = 0; q < GJ_RPT; ++q) w[q] = q == k ? v : w[q];
+}
+
 __global__ __launch_bounds__(1024) void k_small_gj(double* W, int b, int* bad) {
-  __shared__ double a[NB * NB];
-  __shared__ double rowp[NB], colp[NB];
-  __shared__ int perm[NB];
-  __shared__ double wv[16];
-  __shared__ int wi[16];
+  __shared__ double rowp[NB], colp[NB], rowr[NB];
+  __shared__ double cv[8];
+  __shared__ int ci[8];
+  __shared__ int perm[NB], src[NB];
   __shared__ int piv_row;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < b * b; e += blockDim.x) a[e] = W[e];
-  __syncthreads();
+  const int tid = threadIdx.x, j = tid & (NB - 1), g = tid >> 7;
+  double w[GJ_RPT];
+#pragma unroll
+  for (int k = 0; k < GJ_RPT; ++k) {
+    const int i = g + 8 * k;
+    w[k] = (i < b && j < b) ? W[i * b + j] : 0.0;
+  }
   for (int p = 0; p < b; ++p) {
-    // pivot search over rows p .. b-1 of column p: the first two waves cover 128 rows
-    if (wave < 2) {
-      const int i = p + tid;
-      double v = i < b ? fabs(a[i * b + p]) : -1.0;
-      int r = i;
-      for (int o = 32; o > 0; o >>= 1) {
-        const double v2 = __shfl_down(v, o);
-        const int r2 = __shfl_down(r, o);
-        if (v2 > v || (v2 == v && r2 < r)) {
-          v = v2;
-          r = r2;
+    // pivot search in column p: the eight threads holding it reduce their rows >= p
+    if (j == p) {
+      double best = -1.0;
+      int br = p;
+#pragma unroll
+      for (int k = 0; k < GJ_RPT; ++k) {
+        const int i = g + 8 * k;
+        const double v = fabs(w[k]);
+        if (i >= p && i < b && v > best) {
+          best = v;
+          br = i;
         }
       }
-      if (lane == 0) {
-        wv[wave] = v;
-        wi[wave] = r;
-      }
+      cv[g] = best;
+      ci[g] = br;
     }
     __syncthreads();
     if (tid == 0) {
-      int r = wi[0];
-      if (wv[1] > wv[0]) r = wi[1];
-      if (r >= b) r = p;
-      piv_row = r;
-      perm[p] = r;
+      double best = cv[0];
+      int br = ci[0];
+      for (int q = 1; q < 8; ++q)
+        if (cv[q] > best || (cv[q] == best && ci[q] < br)) {
+          best = cv[q];
+          br = ci[q];
+        }
+      piv_row = br;
+      perm[p] = br;
     }
     __syncthreads();
     const int r = piv_row;
-    if (r != p)
-      for (int t = tid; t < b; t += blockDim.x) {
-        const double x = a[p * b + t];
-        a[p * b + t] = a[r * b + t];
-        a[r * b + t] = x;
-      }
+    const int gp = p & 7, kp = p >> 3, gr = r & 7, kr = r >> 3;
+    // rows p and r through LDS: row p's old values to rowp, row r's to rowr
+    if (g == gp) rowp[j] = gj_get(w, kp);
+    if (g == gr) rowr[j] = gj_get(w, kr);
     __syncthreads();
-    const double d = a[p * b + p];
+    if (r != p) {
+      if (g == gp) gj_set(w, kp, rowr[j]);
+      if (g == gr) gj_set(w, kr, rowp[j]);
+    }
+    __syncthreads();
+    // the pivot row (after the exchange) and the pivot column
+    if (g == gp) rowp[j] = gj_get(w, kp);
+    if (j == p)
+#pragma unroll
+      for (int k = 0; k < GJ_RPT; ++k) colp[g + 8 * k] = w[k];
+    __syncthreads();
+    const double d = rowp[p];
     if (tid == 0 && (!(fabs(d) > 0.0) || !isfinite(d))) atomicOr(bad, 1);
     const double ip = 1.0 / d;
-    for (int t = tid; t < b; t += blockDim.x) {
-      rowp[t] = a[p * b + t];
-      colp[t] = a[t * b + p];
-    }
-    __syncthreads();
-    for (int e = tid; e < b * b; e += blockDim.x) {
-      const int i = e / b, j = e % b;
+    const double rj = rowp[j];
+#pragma unroll
+    for (int k = 0; k < GJ_RPT; ++k) {
+      const int i = g + 8 * k;
+      const double ci_ = colp[i];
       double v;
       if (i == p && j == p) v = ip;
-      else if (i == p) v = rowp[j] * ip;
-      else if (j == p) v = -colp[i] * ip;
-      else v = a[e] - colp[i] * rowp[j] * ip;
-      a[e] = v;
+      else if (i == p) v = rj * ip;
+      else if (j == p) v = -ci_ * ip;
+      else v = w[k] - ci_ * rj * ip;
+      w[k] = v;
     }
-    __syncthreads();
+    __syncthreads();  // rowp, colp and the candidates are rewritten by the next step
   }
-  // undo the row exchanges as column exchanges, last first
-  for (int p = b - 1; p >= 0; --p) {
-    const int r = perm[p];
-    if (r != p)
-      for (int i = tid; i < b; i += blockDim.x) {
-        const double x = a[i * b + p];
-        a[i * b + p] = a[i * b + r];
-        a[i * b + r] = x;
-      }
-    __syncthreads();
+  // undo the row exchanges as column exchanges, last first: output column c = column src[c]
+  if (tid == 0) {
+    for (int c = 0; c < b; ++c) src[c] = c;
+    for (int p = b - 1; p >= 0; --p) {
+      const int r = perm[p];
+      const int t = src[p];
+      src[p] = src[r];
+      src[r] = t;
+    }
+    for (int c = 0; c < b; ++c) perm[src[c]] = c;  // perm now maps a source column to its output
   }
-  for (int e = tid; e < b * b; e += blockDim.x) W[e] = a[e];
+  __syncthreads();
+  if (j < b) {
+    const int c = perm[j];
+#pragma unroll
+    for (int k = 0; k < GJ_RPT; ++k) {
+      const int i = g + 8 * k;
+      if (i < b) W[i * b + c] = w[k];
+    }
+  }
 }
 
 // Probe vectors for inverse_residual: X[r][i] = +-1 from an integer hash of (r, i).
