@@ -288,8 +288,10 @@ hipError_t invert_in_place(double* A, int64_t n, double* work, hipStream_t s, in
     op.X = nullptr; op.ldx = 0;
     op.alpha = 1.0; op.beta = 0.0;
     if ((e = gemm_launch(d, &op, 1, nullptr, nullptr, 0, s)) != hipSuccess) return e;
-    // A = A - U R   (n x n, K = b), in place
-    GemmDesc d2{CF64, T_F64, T_F64, T_F64, T_F64, KC, RC, 0, 1};
+    // A = A - U R   (n x n, K = b), in place; 128 x 128 tiles at two workgroups per CU (this
+    // update streams the whole matrix once per pivot block: 0.27 against 0.36 s for the
+    // 13000-orbital inverse with one workgroup per CU)
+    GemmDesc d2{CF64, T_F64, T_F64, T_F64, T_F64, KC, RC, 4, 1};
     GemmOp op2{};
     op2.M = (int)n; op2.N = (int)n; op2.nseg = 1;
     op2.A[0] = U; op2.lda[0] = b;
