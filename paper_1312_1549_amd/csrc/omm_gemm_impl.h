@@ -150,11 +150,14 @@ struct ModeTraits<CBF16X1> : ModeTraits<CBF16X3> {};
 // KC: vector = VEC consecutive k of one row. RC: vector = VEC consecutive rows of one k.
 // TS = unsigned short means pre-split bf16 planes (hi at X, lo at Xlo), copied without conversion.
 // LDS element offset of (row r, k). Padded rows, or (SWZ, BF16x3 with BK = 32) unpadded 64-byte
-// rows whose four 16-byte chunks are rotated by r/4, which keeps the 16 rows read by one
-// quarter-wave on 16 distinct 16-byte bank groups.
+// rows whose four 16-byte chunks are rotated by r/2. A 16-byte-per-lane LDS read is served 16
+// lanes per clock, lanes 8h .. 8h + 7 together with 8h + 16 .. 8h + 23: for a 16 x 16 fragment
+// (lane % 16 = row, lane / 16 = chunk) those are 8 rows at two chunks, and the r/2 rotation puts
+// them on 16 distinct 16-byte bank groups (a rotation by r/4 or r leaves them 2-way
+// conflicted).
 template <bool SWZ, int RS>
 __device__ __forceinline__ int lds_off(int r, int k) {
-  if constexpr (SWZ) return r * RS + ((((k >> 3) + (r >> 2)) & 3) << 3) + (k & 7);
+  if constexpr (SWZ) return r * RS + ((((k >> 3) + (r >> 1)) & 3) << 3) + (k & 7);
   else return r * RS + k;
 }
 
@@ -576,7 +579,7 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
 // ds_write is issued. NS stage buffers rotate: the loads of stage t + NS - 1 are issued right
 // after the barrier that opens stage t, which gives each load NS - 1 compute phases to land. The
 // rotated-chunk row layout of the register path is kept: LDS slot (row r, chunk l % 4) receives
-// logical chunk (l % 4 - l / 16) & 3 of row r. Rows past the matrix edge re-read the last row
+// logical chunk (l % 4 - l / 8) & 3 of row r (r = 16 j + l / 4, so (r / 2) % 4 = (l / 8) % 4). Rows past the matrix edge re-read the last row
 // (their outputs are never stored); a stage that runs past the end of K takes the register path
 // (zero fill). Requires 16-byte aligned plane pointers, leading dimensions that are multiples
 // of 8, and a first segment length that is a multiple of 8 (checked by the launcher).
@@ -628,7 +631,7 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
     for (int j = 0; j < TN; ++j) acc[i][j] = f4{0, 0, 0, 0};
 
   // this lane's row within a 16-row wave chunk, and the logical 8-element chunk it fetches
-  const int lrow = lane >> 2, lchunk = ((lane & 3) - (lane >> 4)) & 3;
+  const int lrow = lane >> 2, lchunk = ((lane & 3) - (lane >> 3)) & 3;
 
   for (int seg = 0; seg < op.nseg; ++seg) {
     int kb, ke;
