@@ -24,6 +24,7 @@
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "omm_internal.h"
 
@@ -584,6 +585,22 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
 // (zero fill). Requires 16-byte aligned plane pointers, leading dimensions that are multiples
 // of 8, and a first segment length that is a multiple of 8 (checked by the launcher).
 constexpr int DMA_BM = 256, DMA_BN = 256, DMA_BK = 32, DMA_PLANE = DMA_BM * DMA_BK;
+
+// f(std::integral_constant<int, i>) for i = 0 .. N - 1, each i a compile-time constant
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+// Loads i = 0 .. n - 1 spread over `span` slots: load i goes after slot i span / n.
+constexpr int loads_in_slot(int g, int n, int span) {
+  int c = 0;
+  for (int i = 0; i < n; ++i) c += i * span / n == g;
+  return c;
+}
 static_assert(DMA_BN == SPARSE_BN && DMA_BK == SPARSE_BK, "block-sparse lists follow this tile");
 static_assert(DMA_BM == DMA_BN, "op_tiles / op_tile enumerate symmetric products on square tiles");
 
@@ -613,6 +630,7 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
   constexpr int WM = 2, TM = DMA_TM, TN = DMA_TN, NT = 512, BK = DMA_BK, RS = DMA_BK;
   constexpr bool ONE_A = one_plane_a(MODE), ONE_B = one_plane_b(MODE);
   constexpr int NBA = ONE_A ? 1 : 2, NBB = ONE_B ? 1 : 2, NPL = NBA + NBB;
+  constexpr int NPROD = (ONE_A && ONE_B) ? 1 : (ONE_A || ONE_B) ? 2 : 3;
   constexpr int DPS = NPL * (DMA_BM * BK * 2 / 1024) / 8;  // 1 KB wave loads per wave per stage
   static_assert(is_bf16_mode(MODE), "direct-to-LDS path: bf16 planes only");
   static_assert(NS * NPL * DMA_PLANE * 2 <= 160 * 1024, "LDS budget");
@@ -696,14 +714,22 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
 #pragma unroll
     for (int st = 0; st < NS - 1; ++st)
       if (st < nst) issue(st);
-    for (int t = 0; t < nst; ++t) {
+    // the stream-K kernel with three products has no registers to spare for the next pair
+    constexpr bool PIPE = !(NPROD == 3 && USER::kind == 1);
+    // One stage. The direct-to-LDS loads of stage t + NS - 1 go into the buffer read in stage
+    // t - 1. With SPREAD they are spread between this stage's MFMA groups, so that no wave
+    // stalls issuing all of them at once while the memory pipeline drains; otherwise they (or
+    // the register path of a partial stage) are issued before the compute.
+    auto run_stage = [&](int t, auto spread_tag) {
+      constexpr bool SPREAD = decltype(spread_tag)::value;
       // this wave's loads of stage t have landed (those of the issued stages after it, up to
       // t + NS - 2, may still be in flight), then every wave's have
       if (NS > 3 && t + 2 < nst && full(t + 2)) wait_vm_lgkm0<(NS > 3 ? 2 * DPS : 0)>();
       else if (NS > 2 && t + 1 < nst && full(t + 1)) wait_vm_lgkm0<(NS > 2 ? DPS : 0)>();
       else wait_vm_lgkm0<0>();
       __builtin_amdgcn_s_barrier();
-      if (t + NS - 1 < nst) issue(t + NS - 1);
+      const int tnext = t + NS - 1;
+      if (!SPREAD && tnext < nst) issue(tnext);
       const lds_t* buf = L + (t % NS) * NPL * DMA_PLANE;
       const lds_t* a0 = buf;
       const lds_t* a1 = buf + (NBA - 1) * DMA_PLANE;
@@ -718,7 +744,6 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
       // from LDS while the MFMAs of pair p run, so a wave waits on LDS once per stage (for its
       // B fragments and first pair) instead of once per pair.
       constexpr int PAIR = 2, NPAIR = TM / PAIR, NAR = ONE_A ? 1 : 2;
-      constexpr int NPROD = (ONE_A && ONE_B) ? 1 : (ONE_A || ONE_B) ? 2 : 3;
       constexpr int NBR = TN * (ONE_B ? 1 : 2);
       static_assert(TM % PAIR == 0, "row blocks come in pairs");
       bf8 ah[2][PAIR], al[2][PAIR], bh[TN], bl[TN];
@@ -742,32 +767,63 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bh[j], acc[i][j], 0, 0, 0);
         }
       };
-      // the stream-K kernel with three products has no registers to spare for the next pair
-      constexpr bool PIPE = !(NPROD == 3 && USER::kind == 1);
-      if constexpr (PIPE) load_pair(0);
+      auto load_b = [&]() {
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int r = wn * TN * 16 + j * 16 + (lane & 15);
-        bh[j] = frag(b0, r);
-        bl[j] = ONE_B ? bh[j] : frag(b1, r);
-      }
-      if constexpr (PIPE) {
+        for (int j = 0; j < TN; ++j) {
+          const int r = wn * TN * 16 + j * 16 + (lane & 15);
+          bh[j] = frag(b0, r);
+          bl[j] = ONE_B ? bh[j] : frag(b1, r);
+        }
+      };
+      // MFMA group g (0 .. 2 NPAIR - 1) is followed by the stage-tnext loads i with
+      // slot(i) = g: spread over all groups with three stages (a load has the rest of this
+      // stage and the whole next one to land), over the first half with two (the rest of this
+      // stage only).
+      constexpr int NGRP = 2 * NPAIR, SPAN = NS > 2 ? NGRP : NGRP / 2;
+      auto slot = [](int i) { return i * SPAN / DPS; };  // == loads_in_slot's rule
+      auto pipelined = [&](auto with_loads) {
+        constexpr bool WL = decltype(with_loads)::value;
+        lds_t* nb = L + (tnext % NS) * NPL * DMA_PLANE;
+        const unsigned kb2 = 2u * (unsigned)kstart(tnext);
+        auto loads_after = [&](int g) {
+          if constexpr (WL) {
+#pragma unroll
+            for (int i = 0; i < DPS; ++i)
+              if (slot(i) == g)
+                __builtin_amdgcn_global_load_lds(
+                    reinterpret_cast<const char*>(plane[i >> 1]) + (off[i] + kb2), nb + dst[i],
+                    16, 0, 0);
+          }
+        };
+        load_pair(0);
+        load_b();
 #pragma unroll
         for (int p = 0; p < NPAIR; ++p) {
           mfma_row(p, 0);
+          loads_after(2 * p);
           if (p + 1 < NPAIR) load_pair(p + 1);
           mfma_row(p, 1);
+          loads_after(2 * p + 1);
         }
         // instruction groups for the scheduler: [reads of pair 0 and B] then, per pair p,
-        // [MFMAs of its first row block] [reads of pair p + 1] [MFMAs of its second row block]
+        // [MFMAs of its first row block] [its loads] [reads of pair p + 1] [MFMAs of its second
+        // row block] [its loads]
         __builtin_amdgcn_sched_group_barrier(0x100, PAIR * NAR + NBR, 0);
-#pragma unroll
-        for (int p = 0; p < NPAIR; ++p) {
+        static_for<NPAIR>([&](auto pc) {
+          constexpr int p = decltype(pc)::value;
+          constexpr int n0 = WL ? loads_in_slot(2 * p, DPS, SPAN) : 0;
+          constexpr int n1 = WL ? loads_in_slot(2 * p + 1, DPS, SPAN) : 0;
           __builtin_amdgcn_sched_group_barrier(0x008, TN * NPROD, 0);
-          if (p + 1 < NPAIR) __builtin_amdgcn_sched_group_barrier(0x100, PAIR * NAR, 0);
+          if constexpr (n0 > 0) __builtin_amdgcn_sched_group_barrier(0x010, n0, 0);
+          if constexpr (p + 1 < NPAIR) __builtin_amdgcn_sched_group_barrier(0x100, PAIR * NAR, 0);
           __builtin_amdgcn_sched_group_barrier(0x008, TN * NPROD, 0);
-        }
+          if constexpr (n1 > 0) __builtin_amdgcn_sched_group_barrier(0x010, n1, 0);
+        });
+      };
+      if constexpr (PIPE) {
+        pipelined(spread_tag);
       } else {
+        load_b();
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
           const int r = wm * TM * 16 + i * 16 + (lane & 15);
@@ -782,7 +838,15 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
           }
         }
       }
+    };
+    // Stages t whose stage t + NS - 1 exists and is full spread their loads: a prefix, since
+    // only the last stage can be partial.
+    int t = 0;
+    if constexpr (PIPE) {
+      const int nfull = nst > 0 && !full(nst - 1) ? nst - 1 : nst;
+      for (; t < nfull - NS + 1; ++t) run_stage(t, std::true_type{});
     }
+    for (; t < nst; ++t) run_stage(t, std::false_type{});
   }
 }
 
