@@ -175,8 +175,10 @@ hipError_t launch_products(const GemmDesc& d, const GemmOp* ops, int nops, const
       hipLaunchKernelGGL(fn, dim3(SK_GRID), dim3(512), 0, s, b, done, a, parts);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess || a.W == 0) return e;
-      sk_fixup_fn fx = dd.tc == T_F64 ? gemm_sk_fixup<double, double> : gemm_sk_fixup<float, float>;
-      if ((dd.tc == T_F64) != (dd.tx == T_F64)) return hipErrorInvalidValue;
+      sk_fixup_fn fx = dd.tc == T_F64   ? gemm_sk_fixup<double, double>
+                       : dd.tx == T_F64 ? gemm_sk_fixup<float, double>
+                                        : gemm_sk_fixup<float, float>;
+      if (dd.tc == T_F64 && dd.tx != T_F64) return hipErrorInvalidValue;
       hipLaunchKernelGGL(fx, dim3(a.T - a.R * SK_GRID, SK_FIX_CHUNKS), dim3(256), 0, s, b, done, a,
                          SK_GRID, (const float*)parts);
       return hipGetLastError();

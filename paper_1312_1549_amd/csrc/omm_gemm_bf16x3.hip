@@ -30,6 +30,8 @@ sk_fn pick_sk_bf16x3(const GemmDesc& d) {
   if (d.la != KC || d.lb != KC || d.ta != T_BF16P || d.tb != T_BF16P) return nullptr;
   if (d.tc == T_F32 && d.tx == T_F32) return pick_sk_kernel<CBF16X3, float, float>();
   if (d.tc == T_F64 && d.tx == T_F64) return pick_sk_kernel<CBF16X3, double, double>();
+  // the gradient: FP32 output, FP64 addend
+  if (d.tc == T_F32 && d.tx == T_F64) return pick_sk_kernel<CBF16X3, float, double>();
   return nullptr;
 }
 

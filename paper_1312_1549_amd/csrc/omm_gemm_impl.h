@@ -714,8 +714,6 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
 #pragma unroll
     for (int st = 0; st < NS - 1; ++st)
       if (st < nst) issue(st);
-    // the stream-K kernel with three products has no registers to spare for the next pair
-    constexpr bool PIPE = !(NPROD == 3 && USER::kind == 1);
     // One stage. The direct-to-LDS loads of stage t + NS - 1 go into the buffer read in stage
     // t - 1. With SPREAD they are spread between this stage's MFMA groups, so that no wave
     // stalls issuing all of them at once while the memory pipeline drains; otherwise they (or
@@ -820,32 +818,14 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
           if constexpr (n1 > 0) __builtin_amdgcn_sched_group_barrier(0x010, n1, 0);
         });
       };
-      if constexpr (PIPE) {
-        pipelined(spread_tag);
-      } else {
-        load_b();
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const int r = wm * TM * 16 + i * 16 + (lane & 15);
-          const bf8 h = frag(a0, r), l = ONE_A ? h : frag(a1, r);
-#pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            if constexpr (!ONE_A)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bh[j], acc[i][j], 0, 0, 0);
-            if constexpr (!ONE_B)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bl[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bh[j], acc[i][j], 0, 0, 0);
-          }
-        }
-      }
+      pipelined(spread_tag);
     };
     // Stages t whose stage t + NS - 1 exists and is full spread their loads: a prefix, since
-    // only the last stage can be partial.
+    // only the last stage can be partial. Two loops, so that each holds one copy of the body
+    // (with both copies in one loop the register allocator spills).
+    const int nfull = nst > 0 && !full(nst - 1) ? nst - 1 : nst;
     int t = 0;
-    if constexpr (PIPE) {
-      const int nfull = nst > 0 && !full(nst - 1) ? nst - 1 : nst;
-      for (; t < nfull - NS + 1; ++t) run_stage(t, std::true_type{});
-    }
+    for (; t < nfull - NS + 1; ++t) run_stage(t, std::true_type{});
     for (; t < nst; ++t) run_stage(t, std::false_type{});
   }
 }
