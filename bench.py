@@ -427,7 +427,43 @@ def copy_kernel(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "check": float(b[-1])}))
 
 
+def vendor_gemm(reps=20):
+    """Context for the GEMM rooflines: the rate of the vendor BF16 GEMM (torch.matmul on
+    hipBLASLt) on the single-pass shapes of the N=13000, M=2000 line search (random bf16 operands,
+    FP32 accumulation). Not part of the method's path; it shows what a tuned library reaches on
+    these shapes against the 2.5 PFLOP/s dense peak."""
+    import torch
+
+    torch.manual_seed(0)
+    out = []
+    shapes = [("[HD|SD], PG: one pass", 2000, 13000, 13000),
+              ("gradient: one pass", 2000, 13000, 4000),
+              ("projections: one pass", 2000, 2000, 13000),
+              ("square reference", 8192, 8192, 8192)]
+    for name, m, n, k in shapes:
+        a = torch.randn(m, k, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(k, n, device="cuda", dtype=torch.bfloat16)
+        for _ in range(3):
+            c = a @ b
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+        out.append({"shape": name, "m": m, "n": n, "k": k, "ms": round(ms, 4),
+                    "tflops": round(tf, 1), "frac": round(tf / 2500.0, 3)})
+        del a, b, c
+    print(json.dumps({"vendor_bf16_gemm": out}))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--vendor-gemm":
+        vendor_gemm()
+        return
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
         print(summarize_rocprof(sys.argv[2]))
         return
