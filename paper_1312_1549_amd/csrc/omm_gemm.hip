@@ -149,6 +149,8 @@ hipError_t launch_products(const GemmDesc& d, const GemmOp* ops, int nops, const
     // block-sparse B lists are read only by the direct-to-LDS tile over the whole K range
     for (int i = 0; i < nops; ++i)
       if (ops[i].nseg != 1 || !ops[i].kidx) return hipErrorInvalidValue;
+    for (int i = 0; i < nops; ++i)  // a column tile's list is staged in LDS
+      if ((ops[i].K[0] + SPARSE_BK - 1) / SPARSE_BK > SPARSE_KL_MAX) return hipErrorInvalidValue;
     if (!is_bf16_mode(dd.compute) || !dma_ok(dd, ops, nops)) return hipErrorInvalidValue;
     dd.tile = 5;
     dd.splitk = 1;

@@ -575,15 +575,20 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
 }
 
 // ---- direct-to-LDS pipeline: bf16 planes, A and B k-contiguous, 256 x 256 tile, 8 waves -----
-// Full K stages go from memory straight into LDS (global_load_lds_dwordx4: lane l of a wave
+// Full K stages go from memory straight into LDS (buffer_load_dwordx4 ... lds: lane l of a wave
 // writes its 16 bytes at the wave's LDS base + 16 l), so no VGPRs hold staged tiles and no
-// ds_write is issued. NS stage buffers rotate: the loads of stage t + NS - 1 are issued right
-// after the barrier that opens stage t, which gives each load NS - 1 compute phases to land. The
-// rotated-chunk row layout of the register path is kept: LDS slot (row r, chunk l % 4) receives
-// logical chunk (l % 4 - l / 8) & 3 of row r (r = 16 j + l / 4, so (r / 2) % 4 = (l / 8) % 4). Rows past the matrix edge re-read the last row
-// (their outputs are never stored); a stage that runs past the end of K takes the register path
-// (zero fill). Requires 16-byte aligned plane pointers, leading dimensions that are multiples
-// of 8, and a first segment length that is a multiple of 8 (checked by the launcher).
+// ds_write is issued. NS stage buffers rotate: the loads of stage t + NS - 1 are issued during
+// stage t, which gives each load up to NS - 1 compute phases to land. The rotated-chunk row
+// layout of the register path is kept: LDS slot (row r, chunk l % 4) receives logical chunk
+// (l % 4 - l / 8) & 3 of row r (r = 16 j + l / 4, so (r / 2) % 4 = (l / 8) % 4). Rows past the
+// matrix edge re-read the last row (their outputs are never stored); a stage that runs past the
+// end of K takes the register path (zero fill). Requires 16-byte aligned plane pointers, leading
+// dimensions that are multiples of 8, and a first segment length that is a multiple of 8
+// (checked by the launcher). The loads take the buffer form rather than the global one: the
+// compiler counts a global load into LDS as both a memory and an LDS operation, and after one
+// it can only wait for all outstanding LDS reads at once, so every K step would wait for its
+// whole first batch of fragment reads before its first MFMA. With the buffer form its LDS waits
+// stay per read; the descriptor's record count (the plane's size) also bounds every load.
 constexpr int DMA_BM = 256, DMA_BN = 256, DMA_BK = 32, DMA_PLANE = DMA_BM * DMA_BK;
 
 // f(std::integral_constant<int, i>) for i = 0 .. N - 1, each i a compile-time constant
@@ -633,12 +638,17 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
   constexpr int NPROD = (ONE_A && ONE_B) ? 1 : (ONE_A || ONE_B) ? 2 : 3;
   constexpr int DPS = NPL * (DMA_BM * BK * 2 / 1024) / 8;  // 1 KB wave loads per wave per stage
   static_assert(is_bf16_mode(MODE), "direct-to-LDS path: bf16 planes only");
-  static_assert(NS * NPL * DMA_PLANE * 2 <= 160 * 1024, "LDS budget");
+  static_assert(NS * NPL * DMA_PLANE * 2 + SPARSE_KL_MAX * 4 <= 160 * 1024, "LDS budget");
   typedef unsigned short lds_t;
   typedef Stager<MODE, unsigned short, KC, DMA_BM, BK, NT, true, ONE_A> SA;
   typedef Stager<MODE, unsigned short, KC, DMA_BN, BK, NT, true, ONE_B> SB;
 
-  __shared__ __attribute__((aligned(16))) lds_t L[NS * NPL * DMA_PLANE];
+  // Stage buffers, then the column tile's K-block list (block-sparse B), read from LDS: a global
+  // load of the next entry would make every stage wait for all of its operand loads in flight.
+  // One LDS object: with a second one the compiler makes every fragment read after a
+  // direct-to-LDS load wait for that load.
+  __shared__ __attribute__((aligned(16))) lds_t L[NS * NPL * DMA_PLANE + 2 * SPARSE_KL_MAX];
+  int* const KL = reinterpret_cast<int*>(L + NS * NPL * DMA_PLANE);
 
   const int m0 = tm * DMA_BM, n0 = tn * DMA_BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -658,6 +668,7 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
     const unsigned short* plane[4];
     int64_t ldp[4];
     int row0[4], rmax[4];
+    __amdgpu_buffer_rsrc_t rs[4];
     {
       int p = 0;
       plane[p] = static_cast<const unsigned short*>(op.A[seg]);
@@ -673,6 +684,12 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
         ldp[p] = op.ldb[seg]; row0[p] = n0; rmax[p] = op.N; ++p;
       }
     }
+    // raw buffer descriptors (stride 0, records = the plane's bytes, gfx9 default format word)
+#pragma unroll
+    for (int p = 0; p < NPL; ++p)
+      rs[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned short*>(plane[p]), (short)0,
+                                                (int)(unsigned)(2 * (int64_t)rmax[p] * ldp[p]),
+                                                0x00020000);
     // per-lane byte offset (32 bits: the plane base stays a wave-uniform scalar) of each of
     // this wave's DPS wave loads; the k offset is added per stage. Wave chunk q = wave + 8 i
     // covers plane q / 16 = i / 2 (8 waves), rows 16 (q % 16) ..
@@ -688,19 +705,23 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
     }
     // dense: stages kb, kb + BK, ...; block-sparse B: the listed K blocks of this column tile
     const bool sparse = op.kptr != nullptr && op.nseg == 1;
-    const int* klist = sparse ? op.kidx + op.kptr[tn] : nullptr;
-    const int nst = sparse ? op.kptr[tn + 1] - op.kptr[tn] : (ke - kb + BK - 1) / BK;
-    auto kstart = [&](int st) { return sparse ? klist[st] * BK : kb + st * BK; };
-    auto full = [&](int st) { return kstart(st) + BK <= ke; };
+    const int nst = sparse ? __builtin_amdgcn_readfirstlane(op.kptr[tn + 1] - op.kptr[tn])
+                           : (ke - kb + BK - 1) / BK;
+    // K offset of stage st and whether the stage is whole, both wave-uniform (the list entry is
+    // read from LDS into a scalar; only the last stage can be partial)
+    auto kstart = [&](int st) {
+      return sparse ? __builtin_amdgcn_readfirstlane(KL[st]) * BK : kb + st * BK;
+    };
+    bool last_full = true;
+    auto full = [&](int st) { return st + 1 < nst || last_full; };
     auto issue = [&](int st) {
       lds_t* buf = L + (st % NS) * NPL * DMA_PLANE;
       const int k0 = kstart(st);
       if (full(st)) {
 #pragma unroll
         for (int i = 0; i < DPS; ++i)
-          __builtin_amdgcn_global_load_lds(
-              reinterpret_cast<const char*>(plane[i >> 1]) + (off[i] + 2u * (unsigned)k0),
-              buf + dst[i], 16, 0, 0);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs[i >> 1], buf + dst[i], 16,
+                                                   off[i] + 2u * (unsigned)k0, 0, 0, 0);
       } else {
         SA sa;
         SB sb;
@@ -711,6 +732,12 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
       }
     };
     __syncthreads();  // the previous segment's readers are done with every buffer
+    if (sparse) {  // nst <= ceil(K / 32) <= SPARSE_KL_MAX (checked by the launcher)
+      const int* klist = op.kidx + op.kptr[tn];
+      for (int e = tid; e < nst; e += NT) KL[e] = klist[e];
+      __syncthreads();
+    }
+    if (nst > 0) last_full = kstart(nst - 1) + BK <= ke;
 #pragma unroll
     for (int st = 0; st < NS - 1; ++st)
       if (st < nst) issue(st);
@@ -788,9 +815,8 @@ __device__ __forceinline__ void gemm_tile_dma_acc(const GemmOp& op, int tm, int 
 #pragma unroll
             for (int i = 0; i < DPS; ++i)
               if (slot(i) == g)
-                __builtin_amdgcn_global_load_lds(
-                    reinterpret_cast<const char*>(plane[i >> 1]) + (off[i] + kb2), nb + dst[i],
-                    16, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs[i >> 1], nb + dst[i], 16,
+                                                         off[i] + kb2, 0, 0, 0);
           }
         };
         load_pair(0);

@@ -90,6 +90,8 @@ size_t gemm_ws_bytes(const GemmDesc& d, const GemmOp* ops, int nops);
 // Block pattern of the block-sparse B lists: 256-wide column tiles of the direct-to-LDS GEMM,
 // 32-deep K blocks.
 constexpr int SPARSE_BN = 256, SPARSE_BK = 32;
+// Longest K-block list of one column tile (K up to 65536): the GEMM stages a tile's list in LDS.
+constexpr int SPARSE_KL_MAX = 2048;
 // flags[t * nkb + kb] = 1 iff some B[r][k] != 0 with r in column tile t and k in K block kb
 // (B is n x n row-major; nkb = ceil(n / SPARSE_BK)).
 hipError_t block_pattern(const double* B, int64_t n, unsigned char* flags, hipStream_t s);
