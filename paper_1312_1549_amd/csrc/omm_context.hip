@@ -373,8 +373,9 @@ int autotune(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, int K, std::pair<int
 
 // One GEMM launch with a tuned (or heuristic) tiling. `tunable` is false for in-place updates,
 // which must not be run more than once.
-// OMM_TILE=<t> pins every GEMM that supports macro tile t to it (no split-K, no autotuning):
-// used to compare tile implementations against each other.
+// OMM_TILE=<t> pins every GEMM that supports macro tile t to it (no split-K, no autotuning), and
+// with t >= 4 the FP64 / FP32 GEMMs to tile 4: used to compare tile implementations against
+// each other.
 int forced_tile() {
   const char* e = getenv("OMM_TILE");
   return (e && e[0]) ? atoi(e) : -1;
@@ -389,11 +390,17 @@ int gemm(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, const int* done, bool tu
   GemmDesc df = d;
   df.tile = ft;
   df.splitk = 1;
-  if (ops[0].kptr) {  // block-sparse B: the launcher runs the direct-to-LDS tile, no split
-    d.tile = 5;
+  if (ops[0].kptr) {  // block-sparse B, no split: the direct-to-LDS tile for the BF16 modes,
+                      // the 128 x 128 tile at two workgroups per CU for FP64 / FP32
+    d.tile = is_bf16_mode(d.compute) ? 5 : 4;
     d.splitk = 1;
   } else if (ft >= 0 && gemm_supported(df)) {
     d = df;
+  } else if (ft >= 4 && !is_bf16_mode(d.compute)) {
+    // the BF16-only tiles pinned: FP64 / FP32 products take tile 4 without split, the tile of
+    // their block-sparse form (so that pinned dense and sparse runs sum in the same order)
+    d.tile = 4;
+    d.splitk = 1;
   } else if (tunable && flops >= 2e9 && autotune_enabled()) {
     TuneKey key{{d.compute, d.ta, d.tb, d.tc, d.tx, d.la, d.lb, M, N, K, nops}};
     std::pair<int, int> choice{-1, 1};
@@ -759,6 +766,11 @@ int initial_products(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* 
   GemmDesc d{compute, et, et, elem_type<T>(), elem_type<T>(), KC, KC, 0, 1};
   GemmOp ops[2] = {make_op2(Mo, N, N, Cop, bf ? pl(c->Hs_p) : dn(Hs, N), w.HC, N),
                    make_op2(Mo, N, N, Cop, bf ? pl(c->S_p) : dn(S, N), w.SC, N)};
+  if (sparse_products(c))  // C [Hs | S] over the non-zero K blocks only (same result)
+    for (int i = 0; i < 2; ++i) {
+      ops[i].kptr = c->kl_ptr[i];
+      ops[i].kidx = c->kl_idx[i];
+    }
   // reduced problem (S~ = I): SC = C, kept as its own copy, which every update then moves
   // exactly like C
   const bool sid = reduced(c);
@@ -1120,6 +1132,11 @@ int resync_fp64(omm_ctx* c) {
   const int Mo = paired_rows(c) ? paired_rows(c) : M;  // rows computed by each product
   GemmOp ops[2] = {make_op(Mo, N, N, w.C, N, c->Hs, N, w.HC, N),
                    make_op(Mo, N, N, w.C, N, c->S, N, w.SC, N)};
+  if (sparse_products(c))  // the FP64 products skip the same zero blocks of Hs and S
+    for (int i = 0; i < 2; ++i) {
+      ops[i].kptr = c->kl_ptr[i];
+      ops[i].kidx = c->kl_idx[i];
+    }
   TRY(gemm(c, d, ops, sid ? 1 : 2, nullptr));
   TRY(fill_pairs(c, w.HC, T_F64, N, N, nullptr, false));
   if (!sid) TRY(fill_pairs(c, w.SC, T_F64, N, N, nullptr, false));

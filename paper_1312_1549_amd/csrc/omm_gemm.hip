@@ -146,13 +146,19 @@ hipError_t launch_products(const GemmDesc& d, const GemmOp* ops, int nops, const
   bool sparse = false;
   for (int i = 0; i < nops; ++i) sparse |= ops[i].kptr != nullptr;
   if (sparse) {
-    // block-sparse B lists are read only by the direct-to-LDS tile over the whole K range
+    // block-sparse B lists are read over the whole K range: BF16 modes by the direct-to-LDS
+    // tile (which stages a column tile's list in LDS), FP64/FP32 by the register tiles (whose
+    // column tiles, 64 to 256 wide, lie within one 256-column list tile)
     for (int i = 0; i < nops; ++i)
       if (ops[i].nseg != 1 || !ops[i].kidx) return hipErrorInvalidValue;
-    for (int i = 0; i < nops; ++i)  // a column tile's list is staged in LDS
-      if ((ops[i].K[0] + SPARSE_BK - 1) / SPARSE_BK > SPARSE_KL_MAX) return hipErrorInvalidValue;
-    if (!is_bf16_mode(dd.compute) || !dma_ok(dd, ops, nops)) return hipErrorInvalidValue;
-    dd.tile = 5;
+    if (is_bf16_mode(dd.compute)) {
+      for (int i = 0; i < nops; ++i)
+        if ((ops[i].K[0] + SPARSE_BK - 1) / SPARSE_BK > SPARSE_KL_MAX) return hipErrorInvalidValue;
+      if (!dma_ok(dd, ops, nops)) return hipErrorInvalidValue;
+      dd.tile = 5;
+    } else if (dd.tile > 4) {
+      return hipErrorInvalidValue;
+    }
     dd.splitk = 1;
   }
   if (dd.tile == 6) {

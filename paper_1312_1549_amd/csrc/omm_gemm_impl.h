@@ -480,18 +480,33 @@ __device__ __forceinline__ void gemm_tile(const GemmOp& op, int tm, int tn, int 
     const bool vb = (SB::PL || LB == KC) && (ldb % SB::VEC) == 0 &&
                     ((reinterpret_cast<uintptr_t>(B) & 15) == 0) &&
                     (!SB::PL || (reinterpret_cast<uintptr_t>(Bl) & 15) == 0);
+    // K steps: kb, kb + BK, ... ; block-sparse B (one segment, no split): the BK-deep parts of
+    // the listed 32-deep K blocks of the 256-column tile that holds this tile's columns (a step
+    // past K loads zeros)
+    constexpr int SUB = SPARSE_BK >= BK ? SPARSE_BK / BK : 1;
+    const bool sparse = op.kptr != nullptr;
+    const int lt = n0 / SPARSE_BN;  // list tile
+    const int* kl = sparse ? op.kidx + op.kptr[lt] : nullptr;
+    const int nsteps = sparse ? __builtin_amdgcn_readfirstlane(op.kptr[lt + 1] - op.kptr[lt]) * SUB
+                              : (ke - kb + BK - 1) / BK;
+    auto kstep = [&](int i) {
+      return sparse ? __builtin_amdgcn_readfirstlane(kl[i / SUB]) * SPARSE_BK + (i % SUB) * BK
+                    : kb + i * BK;
+    };
+    if (nsteps == 0) continue;
     __syncthreads();  // previous segment's readers are done with the buffers
-    sa.load(A, Al, lda, m0, op.M, kb, ke, tid, va);
-    sb.load(B, Bl, ldb, n0, op.N, kb, ke, tid, vb);
+    sa.load(A, Al, lda, m0, op.M, kstep(0), ke, tid, va);
+    sb.load(B, Bl, ldb, n0, op.N, kstep(0), ke, tid, vb);
     sa.store(As[0][0], As[0][NBA - 1], tid);
     sb.store(Bs[0][0], Bs[0][NBB - 1], tid);
     __syncthreads();
     int buf = 0;
-    for (int k0 = kb; k0 < ke; k0 += BK) {
-      const bool more = k0 + BK < ke;
+    for (int step = 0; step < nsteps; ++step) {
+      const bool more = step + 1 < nsteps;
       if (more) {
-        sa.load(A, Al, lda, m0, op.M, k0 + BK, ke, tid, va);
-        sb.load(B, Bl, ldb, n0, op.N, k0 + BK, ke, tid, vb);
+        const int kn = kstep(step + 1);
+        sa.load(A, Al, lda, m0, op.M, kn, ke, tid, va);
+        sb.load(B, Bl, ldb, n0, op.N, kn, ke, tid, vb);
       }
       const lds_t* a0 = As[buf][0];
       const lds_t* b0 = Bs[buf][0];
