@@ -621,6 +621,13 @@ constexpr int loads_in_slot(int g, int n, int span) {
   for (int i = 0; i < n; ++i) c += i * span / n == g;
   return c;
 }
+constexpr bool slots_cover(int n, int span) {  // every load lands in exactly one slot < span
+  int c = 0;
+  for (int g = 0; g < span; ++g) c += loads_in_slot(g, n, span);
+  return c == n;
+}
+static_assert(slots_cover(4, 8) && slots_cover(6, 8) && slots_cover(8, 8) && slots_cover(8, 4),
+              "one-, two- and three-product stages (4, 6, 8 wave loads over 8 or 4 groups)");
 static_assert(DMA_BN == SPARSE_BN && DMA_BK == SPARSE_BK, "block-sparse lists follow this tile");
 static_assert(DMA_BM == DMA_BN, "op_tiles / op_tile enumerate symmetric products on square tiles");
 
