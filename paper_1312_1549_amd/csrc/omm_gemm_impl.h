@@ -1021,27 +1021,45 @@ __global__ __launch_bounds__(256) void gemm_sk_fixup(GemmBatch batch, const int*
   int tm, tn;
   const GemmOp& op = *sk_locate(batch, a.nops, a.R * G + q, tm, tn);
   constexpr int PER = DMA_BM * DMA_BN / SK_FIX_CHUNKS;
-  for (int f = blockIdx.y * PER + threadIdx.x; f < (blockIdx.y + 1) * PER; f += 256) {
-    // the parts are added in K order; four loads are in flight at a time
-    double sum = 0.0;
+  constexpr int U = 4;  // entries per thread and pass, 256 apart (consecutive threads keep
+                        // consecutive entries, so loads and stores stay coalesced)
+  static_assert(PER % (U * 256) == 0, "whole passes");
+  for (int f0 = blockIdx.y * PER + threadIdx.x; f0 < (blockIdx.y + 1) * PER; f0 += U * 256) {
+    // the parts are added in K order, U entries at a time (2 U loads in flight)
+    double sum[U];
+#pragma unroll
+    for (int c = 0; c < U; ++c) sum[c] = 0.0;
     int k = 0;
-    for (; k + 4 <= n; k += 4) {
-      float v[4];
+    for (; k + 2 <= n; k += 2) {
+      float v[2][U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = parts[(int64_t)slot[k + u] * (DMA_BM * DMA_BN) + f];
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) sum += (double)v[u];
+        for (int c = 0; c < U; ++c)
+          v[u][c] = parts[(int64_t)slot[k + u] * (DMA_BM * DMA_BN) + f0 + 256 * c];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int c = 0; c < U; ++c) sum[c] += (double)v[u][c];
     }
-    for (; k < n; ++k) sum += (double)parts[(int64_t)slot[k] * (DMA_BM * DMA_BN) + f];
-    const int e = f >> 9, tid = f & 511;  // slot entry and the kernel thread that wrote it
-    const int wave = tid >> 6, lane = tid & 63;
-    const int i = e / (DMA_TN * 4), j = (e / 4) % DMA_TN, r = e % 4;
-    const int row = tm * DMA_BM + (wave % 2) * DMA_TM * 16 + i * 16 + 4 * (lane >> 4) + r;
-    const int col = tn * DMA_BN + (wave / 2) * DMA_TN * 16 + j * 16 + (lane & 15);
-    if (row < op.M && col < op.N) {
-      double v = op.alpha * sum;
-      if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
-      store_out<TC>(op, row, col, v);
+    if (k < n) {
+#pragma unroll
+      for (int c = 0; c < U; ++c)
+        sum[c] += (double)parts[(int64_t)slot[k] * (DMA_BM * DMA_BN) + f0 + 256 * c];
+    }
+#pragma unroll
+    for (int c = 0; c < U; ++c) {
+      const int f = f0 + 256 * c;
+      const int e = f >> 9, tid = f & 511;  // slot entry and the kernel thread that wrote it
+      const int wave = tid >> 6, lane = tid & 63;
+      const int i = e / (DMA_TN * 4), j = (e / 4) % DMA_TN, r = e % 4;
+      const int row = tm * DMA_BM + (wave % 2) * DMA_TM * 16 + i * 16 + 4 * (lane >> 4) + r;
+      const int col = tn * DMA_BN + (wave / 2) * DMA_TN * 16 + j * 16 + (lane & 15);
+      if (row < op.M && col < op.N) {
+        double v = op.alpha * sum[c];
+        if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
+        store_out<TC>(op, row, col, v);
+      }
     }
   }
 }
