@@ -100,12 +100,13 @@ enum {
 int omm_set_flavour(omm_ctx *ctx, int flavour);
 
 /* Block-sparse operator products (the sparse x dense products of Secs. 2.6 and 3, applied to
- * [HD | SD] = D [Hs | S] of OMM_BF16X3 in the dense flavour; default off). The finite-range
- * basis leaves most of Hs and S zero: for every 256-column tile of the product the library lists
- * the 32-deep K blocks in which the operator is not all zero (built once per Hs and S) and
- * multiplies over those only. The skipped blocks contribute exact zeros, so the results are the
- * dense products (up to the sign of zero) and the iterates do not change. Other modes and the
- * Cholesky flavour (whose H~ is dense) ignore it. */
+ * every product with Hs or S of OMM_BF16X3 in the dense flavour: [HD | SD] = D [Hs | S] in each
+ * line search, and C [Hs | S] in FP64 when a phase starts and at each resynchronization; default
+ * off). The finite-range basis leaves most of Hs and S zero: for every 256-column tile of the
+ * product the library lists the 32-deep K blocks in which the operator is not all zero (built
+ * once per Hs and S) and multiplies over those only. The skipped blocks contribute exact zeros,
+ * so the results are the dense products (up to the sign of zero) and the iterates do not change.
+ * Other modes and the Cholesky flavour (whose H~ is dense) ignore it. */
 int omm_set_sparse(omm_ctx *ctx, int on);
 /* Fraction of K blocks listed for Hs (density[0]) and S (density[1]) after a minimization with
  * sparse products on; OMM_E_STATE otherwise. */
