@@ -123,14 +123,14 @@ int balloc(omm_batch* b, P** p, size_t n) {
 
 template <typename P>
 void bfree(P*& p) {
-  if (p) hipFree(p);
+  if (p) (void)hipFree(p);
   p = nullptr;
 }
 
 void free_list(OpList& L) {
   bfree(L.d_ops);
   bfree(L.d_tiles);
-  if (L.d_done) hipFree((void*)L.d_done);
+  if (L.d_done) (void)hipFree((void*)L.d_done);
   L.d_done = nullptr;
   L.cap = 0;
 }
@@ -302,8 +302,8 @@ int tune_list(omm_batch* b, OpList& L) {
       best_t = t;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   BTRY(upload_list(b, L, best_t));
   L.tuned = true;
   return OMM_OK;
@@ -408,8 +408,8 @@ int batch_iteration(omm_batch* b, PhaseLists& L, const SysDev* d_sys, int k) {
 }
 
 void drop_graph(omm_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
 }
@@ -497,7 +497,7 @@ int run_phase(omm_batch* b, bool f64, double tol, int max_iter) {
     hipGraph_t g = nullptr;
     hipError_t ec = hipStreamEndCapture(b->stream, &g);
     if (r1 != OMM_OK || r2 != OMM_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return r1 != OMM_OK ? r1 : r2;
     }
     BHIP(b, ec);
@@ -556,7 +556,7 @@ int omm_batch_create(int nsys, const int64_t* N, const int64_t* M, omm_batch** o
 
 int omm_batch_destroy(omm_batch* b) {
   if (!b) return OMM_E_ARG;
-  if (b->stream) hipStreamSynchronize(b->stream);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_graph(b);
   for (BSys& s : b->sys) free_sys(s);
   for (OpList* L : b->L32.all()) free_list(*L);
@@ -565,8 +565,8 @@ int omm_batch_destroy(omm_batch* b) {
   bfree(b->d_sys);
   bfree(b->d_sys64);
   bfree(b->inv_work);
-  if (b->st_host) hipHostFree(b->st_host);
-  if (b->stream) hipStreamDestroy(b->stream);
+  if (b->st_host) (void)hipHostFree(b->st_host);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return OMM_OK;
 }

@@ -170,7 +170,7 @@ int dalloc(omm_ctx* c, P** p, size_t count) {
 
 template <typename P>
 void dfree(P*& p) {
-  if (p) hipFree(p);
+  if (p) (void)hipFree(p);
   p = nullptr;
 }
 
@@ -366,8 +366,8 @@ int autotune(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, int K, std::pair<int
       best_ms = t_best[i];
       *best = cands[i];
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return OMM_OK;
 }
 
@@ -1020,8 +1020,8 @@ int ensure_trace(omm_ctx* c, int need) {
 }
 
 void drop_graph(omm_ctx* c) {
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   c->graph_exec = nullptr;
   c->graph = nullptr;
   c->graph_parity = -1;
@@ -1043,7 +1043,7 @@ int capture_pair(omm_ctx* c, Work<T>& w, int compute, const T* Hs, const T* S, c
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->stream, &g);
   if (r != OMM_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return r;
   }
   HIPCHK(c, e);
@@ -1421,7 +1421,7 @@ int omm_create(int64_t N, int64_t M, omm_ctx** out) {
 
 int omm_destroy(omm_ctx* c) {
   if (!c) return OMM_E_ARG;
-  hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
   dfree(c->H); dfree(c->S); dfree(c->T); dfree(c->Hs); dfree(c->P);
   dfree(c->Hs32); dfree(c->S32); dfree(c->P32);
@@ -1438,9 +1438,9 @@ int omm_destroy(omm_ctx* c) {
     dfree(c->kl_ptr[i]);
     dfree(c->kl_idx[i]);
   }
-  if (c->st_host) hipHostFree(c->st_host);
-  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
-  if (c->own) hipStreamDestroy(c->own);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->own) (void)hipStreamDestroy(c->own);
   delete c;
   return OMM_OK;
 }
