@@ -242,6 +242,40 @@ def test_odd_sizes_take_the_unvectorized_paths(lib_ok, precision):
         np.testing.assert_allclose(solver.energy_trace()[:21], ref.energies[:21], rtol=1e-10)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("n", [1, 4])
+def test_single_wannier_function(lib_ok, precision, n):
+    """The smallest problems: one Wannier function (M = 1). Over a single orbital (N = 1, h =
+    -0.7, s = 1) the functional is 4c^2 h - 2c^4 h with its minimum 2h at c^2 = 1/s (Secs. 2.1,
+    2.2); over 2 atoms x 2 orbitals (N = 4) the minimum is 2 (eps_1 - eta) with eta between the
+    two lowest levels. Every product is a single partial tile and K is shorter than one K step."""
+    if n == 1:
+        H, S, T = np.array([[-0.7]]), np.array([[1.0]]), np.array([[1.5]])
+        C0 = np.array([[0.3]])
+        eta, E_ref = 0.0, -1.4
+    else:
+        rng = np.random.default_rng(41)
+        pos = lattice_positions((2, 1, 1), 2.5)
+        pos = pos + rng.uniform(-0.2, 0.2, size=pos.shape)
+        sy = make_system(pos, 2, 6.0, 1, rng, name="tiny", eta=0.0, tau=10.0, seed=41)
+        H, S, T = sy.H, sy.S, sy.T
+        C0 = start_coefficients(S, 1, 42)
+        w = brute.generalized_eigh_lapack(H, S)[0]
+        eta = float(w[1] - 0.25 * (w[1] - w[0]))
+        E_ref = brute.closed_form_energy(w, 1, eta)
+    _say(f"single WF N={n} M=1 {precision}")
+    solver = lib_ok(n, 1, precision=precision, refine=precision != "fp32")
+    solver.set_HS(H, S, T)
+    status = solver.minimize(C0, eta=eta, tau=10.0, tol=1e-14, max_iter=500)
+    assert status == 0
+    tolr = 1e-5 if precision == "fp32" else 1e-10
+    assert abs(solver.energy() - E_ref) <= tolr * abs(E_ref)
+    if precision == "fp64":
+        ref = oracle.minimize(H, S, T, C0, eta, 10.0, 0.0, 3)
+        np.testing.assert_allclose(solver.energy_trace()[:4], ref.energies[:4], rtol=1e-10)
+    solver.close()
+
+
 @pytest.mark.parametrize("M", [37, 40])
 @pytest.mark.parametrize("refine", [True, False])
 def test_direct_to_lds_tile_matches_register_tile(lib_ok, M, refine, monkeypatch):
