@@ -118,9 +118,14 @@ int omm_set_stream(omm_ctx *ctx, void *hip_stream);
 /* Hamiltonian, overlap and (nullable) kinetic matrices of the generalized eigenproblem
  * H c = eps S c (Sec. 2.1, Eq. 1). Host pointers, N*N each, copied in. T is needed only for a
  * finite tau > 0 (Eq. 17). Checked for finite values and symmetry (relative 1e-10):
- * OMM_E_NONFINITE / OMM_E_ASYMMETRIC. Invalidates the cached shift and preconditioner. */
+ * OMM_E_NONFINITE / OMM_E_ASYMMETRIC (the previous inputs then stay). Ends the active
+ * minimization and drops the cached shift Hs = H - eta S and everything derived from it. When
+ * S and T are bit for bit those of the previous call (an SCF step at a fixed geometry, Sec. 3),
+ * what derives from them alone is kept: the preconditioner P, the Cholesky factor of the
+ * reduced flavour, the bf16 planes, FP32 copy and K-block list of S; a new S or T drops those
+ * too. */
 int omm_set_HS(omm_ctx *ctx, const double *H, const double *S, const double *T);
-/* Same with device pointers (copied device-to-device, validated on the device). */
+/* Same with device pointers (validated on the device, then copied device-to-device). */
 int omm_set_HS_device(omm_ctx *ctx, const double *dH, const double *dS, const double *dT);
 
 /* CG minimization of Eq. 8 from C0 (host, M*N; NULL resumes from the context's current C).
@@ -179,7 +184,8 @@ int omm_backward_device_noalloc(omm_ctx *ctx, double gE, double *d_gH, double *d
 /* Current C (host M*N), HW and SW (host M*M each; either may be NULL). */
 int omm_get_C(omm_ctx *ctx, double *C);
 int omm_get_subspace(omm_ctx *ctx, double *HW, double *SW);
-/* Preconditioner of the last minimization (host N*N); OMM_E_STATE if none was used. */
+/* Preconditioner of the last minimization (host N*N), kept across omm_set_HS calls that leave S
+ * and T unchanged; OMM_E_STATE if none was used or a new S or T dropped it. */
 int omm_get_preconditioner(omm_ctx *ctx, double *P);
 
 /* Line searches of the last minimize call (both phases) and the last relative change. */
@@ -246,7 +252,8 @@ int omm_batch_set_mixed_tol(omm_batch *b, double tol);
 /* Line searches of the last omm_batch_minimize per system (nsys entries each, either pointer
  * nullable): in the FP32 phase and in the FP64 phase. */
 int omm_batch_phase_iterations(omm_batch *b, int *iters32, int *iters64);
-/* System i: host H, S, T (N_i*N_i each; T nullable as for omm_set_HS). */
+/* System i: host H, S, T (N_i*N_i each; T nullable as for omm_set_HS). The system keeps its
+ * preconditioner when S and T are bit for bit those of its previous call. */
 int omm_batch_set_HS(omm_batch *b, int i, const double *H, const double *S, const double *T);
 /* C0[i]: host M_i*N_i start of system i (NULL entry: resume from its current C). eta, tau:
  * arrays of nsys values; max_iter bounds each phase. Returns OMM_OK if every system converged,

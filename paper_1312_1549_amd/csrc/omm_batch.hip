@@ -78,6 +78,7 @@ struct omm_batch {
   SysDev* d_sys64 = nullptr;    // FP64 phase
   double* inv_work = nullptr;
   size_t inv_cap = 0;
+  int* d_cmp = nullptr;  // change flag of omm_batch_set_HS's S / T comparison
   PhaseLists L32, L64;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -565,6 +566,7 @@ int omm_batch_destroy(omm_batch* b) {
   bfree(b->d_sys);
   bfree(b->d_sys64);
   bfree(b->inv_work);
+  bfree(b->d_cmp);
   if (b->st_host) (void)hipHostFree(b->st_host);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -588,19 +590,30 @@ int omm_batch_set_HS(omm_batch* b, int i, const double* H, const double* S, cons
   const size_t nn = (size_t)n * n;
   BTRY(balloc(b, &s.H, nn));
   BTRY(balloc(b, &s.S, nn));
-  BHIP(b, hipMemcpyAsync(s.H, H, nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemcpyAsync(s.S, S, nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
-  BHIP(b, symmetrize(s.H, n, b->stream));
-  BHIP(b, symmetrize(s.S, n, b->stream));
-  s.have_T = T != nullptr;
-  if (T) {
-    BTRY(balloc(b, &s.T, nn));
-    BHIP(b, hipMemcpyAsync(s.T, T, nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
-    BHIP(b, symmetrize(s.T, n, b->stream));
+  BTRY(balloc(b, &s.Hs64, nn));
+  BTRY(balloc(b, &b->d_cmp, 1));
+  if (T) BTRY(balloc(b, &s.T, nn));
+  // S and T go in through Hs (rebuilt from H and S by the next setup) and are compared with the
+  // stored copies: when neither changed bit for bit (an SCF step at a fixed geometry) the
+  // system keeps its preconditioner.
+  const bool compare = s.have_HS && (T != nullptr) == s.have_T;
+  int diff = compare ? 0 : 1;
+  BHIP(b, hipMemcpyAsync(b->d_cmp, &diff, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  double* dsts[2] = {s.S, s.T};
+  const double* srcs[2] = {S, T};
+  for (int k = 0; k < 2; ++k) {
+    if (!srcs[k]) continue;
+    BHIP(b, hipMemcpyAsync(s.Hs64, srcs[k], nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, symmetrize(s.Hs64, n, b->stream));
+    BHIP(b, copy_compare_f64(s.Hs64, dsts[k], (int64_t)nn, b->d_cmp, b->stream));
   }
+  BHIP(b, hipMemcpyAsync(&diff, b->d_cmp, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipMemcpyAsync(s.H, H, nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, symmetrize(s.H, n, b->stream));
   BHIP(b, hipStreamSynchronize(b->stream));
+  s.have_T = T != nullptr;
   s.have_HS = true;
-  s.p_kind = -1;
+  if (diff) s.p_kind = -1;
   drop_graph(b);
   return OMM_OK;
 }

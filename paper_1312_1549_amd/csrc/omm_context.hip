@@ -469,17 +469,24 @@ int ensure_inputs(omm_ctx* c) {
   return OMM_OK;
 }
 
-void invalidate(omm_ctx* c) {
+// New inputs end the active minimization. H changes with every omm_set_HS, and with it
+// Hs = H - eta S (or H~), its planes, FP32 copy and K-block list. What derives from S and T
+// alone (P, its planes and FP32 copy, the Cholesky factor, S's planes, FP32 copy and K-block
+// list) stays valid when neither changed: an SCF loop that updates H at a fixed geometry keeps
+// its preconditioner (Sec. 3 reuses the previous step's coefficients the same way).
+void invalidate(omm_ctx* c, bool s_or_t_changed) {
   drop_graph(c);
-  c->l_valid = false;
-  c->kl_valid[0] = c->kl_valid[1] = false;
   c->phase_active = false;
   c->phase_mixed64 = false;
+  c->kl_valid[0] = false;
   c->hsp_valid = false;
-  c->sp_valid = false;
-  c->pp_valid = false;
   c->hs_valid = false;
   c->hs32_valid = false;
+  if (!s_or_t_changed) return;
+  c->l_valid = false;
+  c->kl_valid[1] = false;
+  c->sp_valid = false;
+  c->pp_valid = false;
   c->s32_valid = false;
   c->p_kind = -1;
   c->p32_valid = false;
@@ -1517,6 +1524,36 @@ int omm_set_stream(omm_ctx* c, void* s) {
   return OMM_OK;
 }
 
+// Copies the symmetrized S and T in from `src_S`, `src_T` (device, or host through the Hs
+// buffer as staging: Hs is rebuilt from H and S before it is read again) and reports whether
+// either changed bit for bit; with no earlier S and T (or T added or dropped) they count as
+// changed.
+int load_S_T(omm_ctx* c, const double* src_S, const double* src_T, bool host, bool* changed) {
+  const int64_t n = c->N;
+  const size_t nn = (size_t)n * n, bytes = nn * sizeof(double);
+  const bool compare = c->have_HS && (src_T != nullptr) == c->have_T;
+  if (src_T) TRY(dalloc(c, &c->T, nn));
+  TRY(dalloc(c, &c->flags, 8));
+  TRY(dalloc(c, &c->Hs, nn));
+  c->hs_valid = false;
+  int diff = compare ? 0 : 1;
+  HIPCHK(c, hipMemcpyAsync(c->flags + 2, &diff, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  double* dsts[2] = {c->S, c->T};
+  const double* srcs[2] = {src_S, src_T};
+  for (int k = 0; k < 2; ++k) {
+    if (!srcs[k]) continue;
+    // staged and symmetrized first, so that the stored copy is compared with what would be stored
+    HIPCHK(c, hipMemcpyAsync(c->Hs, srcs[k], bytes,
+                             host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, symmetrize(c->Hs, n, c->stream));
+    HIPCHK(c, copy_compare_f64(c->Hs, dsts[k], (int64_t)nn, c->flags + 2, c->stream));
+  }
+  HIPCHK(c, hipMemcpyAsync(&diff, c->flags + 2, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *changed = diff != 0;
+  return OMM_OK;
+}
+
 int omm_set_HS(omm_ctx* c, const double* H, const double* S, const double* T) {
   if (!c) return OMM_E_ARG;
   if (!H || !S) return fail(c, OMM_E_ARG, "H and S are required");
@@ -1533,21 +1570,16 @@ int omm_set_HS(omm_ctx* c, const double* H, const double* S, const double* T) {
   }
   TRY(ensure_inputs(c));
   const size_t bytes = (size_t)n * n * sizeof(double);
-  HIPCHK(c, hipMemcpyAsync(c->H, H, bytes, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->S, S, bytes, hipMemcpyHostToDevice, c->stream));
-  c->have_T = T != nullptr;
-  if (T) {
-    TRY(dalloc(c, &c->T, (size_t)n * n));
-    HIPCHK(c, hipMemcpyAsync(c->T, T, bytes, hipMemcpyHostToDevice, c->stream));
-  }
   // Validated to 1e-10; store exactly symmetric copies so that every operator product may read
   // rows in place of columns.
+  bool st_changed = true;
+  TRY(load_S_T(c, S, T, true, &st_changed));
+  HIPCHK(c, hipMemcpyAsync(c->H, H, bytes, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, symmetrize(c->H, n, c->stream));
-  HIPCHK(c, symmetrize(c->S, n, c->stream));
-  if (T) HIPCHK(c, symmetrize(c->T, n, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->have_T = T != nullptr;
   c->have_HS = true;
-  invalidate(c);
+  invalidate(c, st_changed);
   return OMM_OK;
 }
 
@@ -1557,14 +1589,7 @@ int omm_set_HS_device(omm_ctx* c, const double* dH, const double* dS, const doub
   const int64_t n = c->N;
   TRY(ensure_inputs(c));
   TRY(dalloc(c, &c->flags, 8));
-  const size_t bytes = (size_t)n * n * sizeof(double);
-  HIPCHK(c, hipMemcpyAsync(c->H, dH, bytes, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->S, dS, bytes, hipMemcpyDeviceToDevice, c->stream));
-  if (dT) {
-    TRY(dalloc(c, &c->T, (size_t)n * n));
-    HIPCHK(c, hipMemcpyAsync(c->T, dT, bytes, hipMemcpyDeviceToDevice, c->stream));
-  }
-  const double* mats[3] = {c->H, c->S, dT ? c->T : nullptr};
+  const double* mats[3] = {dH, dS, dT};
   const char* names[3] = {"H", "S", "T"};
   for (int i = 0; i < 3; ++i) {
     if (!mats[i]) continue;
@@ -1573,22 +1598,18 @@ int omm_set_HS_device(omm_ctx* c, const double* dH, const double* dS, const doub
     HIPCHK(c, validate_symmetric(mats[i], n, 1e-10, c->flags, c->stream));
     HIPCHK(c, hipMemcpyAsync(h, c->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (h[0]) {
-      c->have_HS = false;
-      return fail(c, OMM_E_NONFINITE, std::string(names[i]) + " has a non-finite entry");
-    }
-    if (h[1]) {
-      c->have_HS = false;
-      return fail(c, OMM_E_ASYMMETRIC, std::string(names[i]) + " is not symmetric");
-    }
+    if (h[0]) return fail(c, OMM_E_NONFINITE, std::string(names[i]) + " has a non-finite entry");
+    if (h[1]) return fail(c, OMM_E_ASYMMETRIC, std::string(names[i]) + " is not symmetric");
   }
+  const size_t bytes = (size_t)n * n * sizeof(double);
+  bool st_changed = true;
+  TRY(load_S_T(c, dS, dT, false, &st_changed));
+  HIPCHK(c, hipMemcpyAsync(c->H, dH, bytes, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, symmetrize(c->H, n, c->stream));
-  HIPCHK(c, symmetrize(c->S, n, c->stream));
-  if (dT) HIPCHK(c, symmetrize(c->T, n, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->have_T = dT != nullptr;
   c->have_HS = true;
-  invalidate(c);
+  invalidate(c, st_changed);
   return OMM_OK;
 }
 

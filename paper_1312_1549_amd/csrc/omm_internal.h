@@ -138,6 +138,8 @@ hipError_t pair_rows(void* X, bool f64, int64_t ld, unsigned short* hi, unsigned
                      int64_t ldp, int rh, int h, const DevState* st, hipStream_t s);
 hipError_t convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 hipError_t copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
+// dst = src, setting *diff to 1 when any element's bits change (*diff is not cleared)
+hipError_t copy_compare_f64(const double* src, double* dst, int64_t n, int* diff, hipStream_t s);
 hipError_t validate_symmetric(const double* A, int64_t n, double rtol, int* flags, hipStream_t s);
 hipError_t symmetrize(double* A, int64_t n, hipStream_t s);
 

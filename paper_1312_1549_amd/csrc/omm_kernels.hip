@@ -1133,6 +1133,22 @@ hipError_t convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t
   return hipGetLastError();
 }
 
+// dst = src; *diff = 1 if any element changes (bit pattern), else *diff is left as it was
+__global__ void k_copy_compare(const double* src, double* dst, int64_t n, int* diff) {
+  bool changed = false;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    const double v = src[i];
+    changed |= __double_as_longlong(v) != __double_as_longlong(dst[i]);
+    dst[i] = v;
+  }
+  if (__any(changed) && (threadIdx.x & 63) == 0) atomicOr(diff, 1);
+}
+
+hipError_t copy_compare_f64(const double* src, double* dst, int64_t n, int* diff, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_compare, dim3(ew_blocks(n)), dim3(NT), 0, s, src, dst, n, diff);
+  return hipGetLastError();
+}
+
 hipError_t copy_f64(const double* src, double* dst, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL((k_convert<double, double>), dim3(ew_blocks(n)), dim3(NT), 0, s, src, dst, n);
   return hipGetLastError();

@@ -61,13 +61,16 @@ def test_fp32_then_fp64_batch_reaches_closed_forms(torch, systems):
     assert np.all(err <= 1e-8)
     assert np.all(it32 > 0) and np.all(it64 > 0)
     assert np.array_equal(b.iterations(), it32 + it64)
-    # SCF-like warm start from the previous minimizer after H += 1e-3 sym(N(0,1))
+    # SCF-like warm start from the previous minimizer after H += 1e-3 sym(N(0,1)); system 0
+    # also gets a new S (scaled by 1.001), so its preconditioner is rebuilt while the others
+    # keep theirs
     Cs = [b.get_C(i) for i in range(len(xs))]
     refs_w = []
     for i, x in enumerate(xs):
         Hp = perturb_hamiltonian(x.H, 400 + i)
-        b.set_HS(i, Hp, x.S, x.T)
-        w = brute.generalized_eigh_lapack(Hp, x.S, x.M + 1)[0]
+        Sp = x.S * 1.001 if i == 0 else x.S
+        b.set_HS(i, Hp, Sp, x.T)
+        w = brute.generalized_eigh_lapack(Hp, Sp, x.M + 1)[0]
         refs_w.append(brute.closed_form_energy(w, x.M, x.eta))
     st = b.minimize(Cs, etas, taus, 1e-13, 5000)
     err_w = _errors(b.energies(), np.array(refs_w))

@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 from oracle import brute, omm as oracle
-from synth import config_system, make_system, lattice_positions, start_coefficients
+from synth import (config_system, lattice_positions, make_system, perturb_hamiltonian,
+                   start_coefficients)
 
 pytestmark = pytest.mark.gpu
 
@@ -240,6 +241,72 @@ def test_odd_sizes_take_the_unvectorized_paths(lib_ok, precision):
     if precision == "fp64":
         ref = oracle.minimize(s.H, s.S, s.T, C0, eta, 10.0, 0.0, 20)
         np.testing.assert_allclose(solver.energy_trace()[:21], ref.energies[:21], rtol=1e-10)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def test_new_H_keeps_the_preconditioner_new_S_or_T_rebuilds_it(lib_ok, c1):
+    """SCF reuse (Sec. 3: the next SCF step starts from the previous coefficients): omm_set_HS
+    with a new H but the same S and T keeps P = (S + T/tau)^-1 (Sec. 2.4, Eq. 17), which stays
+    readable before the next minimization; a new S or T drops it, and the next minimization
+    builds the inverse of the new S + T/tau. Every minimum matches its closed form."""
+    from paper_1312_1549_amd import OMMError
+
+    s, C0, w = c1
+    eta, tau = 0.5, 10.0
+    _say("set_HS reuse of P, c1 fp64")
+    solver = lib_ok(s.N, s.M, precision="fp64")
+
+    def run(H, S, T):
+        solver.minimize(C0, eta=eta, tau=tau, tol=1e-14, max_iter=5000)
+        wv = brute.generalized_eigh_lapack(H, S)[0]
+        E_ref = brute.closed_form_energy(wv, s.M, eta)
+        assert abs(solver.energy() - E_ref) <= 1e-10 * abs(E_ref)
+        P = solver.preconditioner()
+        assert _rel(P, np.linalg.inv(S + T / tau)) < 1e-11
+        return P
+
+    solver.set_HS(s.H, s.S, s.T)
+    P1 = run(s.H, s.S, s.T)
+    H2 = perturb_hamiltonian(s.H, 7)
+    solver.set_HS(H2, s.S, s.T)  # same S, T: P kept
+    assert np.array_equal(solver.preconditioner(), P1)
+    run(H2, s.S, s.T)
+    S2 = s.S + 0.05 * np.eye(s.N)
+    solver.set_HS(H2, S2, s.T)  # new S: P dropped until the next minimization
+    with pytest.raises(OMMError) as e:
+        solver.preconditioner()
+    assert e.value.code == -2
+    run(H2, S2, s.T)
+    T2 = 1.1 * s.T
+    solver.set_HS(H2, S2, T2)  # new T
+    with pytest.raises(OMMError):
+        solver.preconditioner()
+    run(H2, S2, T2)
+    solver.close()
+
+
+@pytest.mark.parametrize("flavour,sparse", [("cholesky", False), ("dense", True)])
+def test_new_H_with_kept_S_data(lib_ok, c2, flavour, sparse):
+    """What else derives from S alone survives a new H and must still pair with it: the
+    Cholesky factor (H~ = L^-1 Hs L^-T is rebuilt from the new H) and the K-block lists of the
+    block-sparse products (the list of Hs is rebuilt: the perturbed H is dense). The minima
+    match the closed forms of each (H, S) to 1e-8; then a new S is picked up as well."""
+    s, C0, w = c2
+    eta, tau = 0.5, 10.0
+    _say(f"set_HS reuse flavour={flavour} sparse={sparse} c2")
+    solver = lib_ok(s.N, s.M, precision="bf16x3", refine=True, flavour=flavour, sparse=sparse)
+    H2 = perturb_hamiltonian(s.H, 8)
+    S2 = s.S + 0.05 * np.eye(s.N)
+    for H, S in ((s.H, s.S), (H2, s.S), (H2, S2)):
+        solver.set_HS(H, S, s.T)
+        solver.minimize(C0, eta=eta, tau=tau, tol=1e-13, max_iter=6000)
+        wv = brute.generalized_eigh_lapack(H, S, s.M + 1)[0]
+        E_ref = brute.closed_form_energy(wv, s.M, eta)
+        assert abs(solver.energy() - E_ref) <= 1e-8 * abs(E_ref)
+    solver.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
