@@ -13,6 +13,8 @@ namespace omm {
 namespace {
 
 constexpr int NT = 256;
+// block-reduction scratch: up to NCOEF values at once (block_sums), one slot per wave each
+constexpr int SH_SUMS = NCOEF * (NT / 64);
 
 // Sum of `v` over the block (FP64, fixed order). Result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -25,6 +27,29 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   if (threadIdx.x == 0)
     for (int i = 0; i < NT / 64; ++i) t += sh[i];
   return t;
+}
+
+// block_sum of W values at once (each in block_sum's order: the same results), with one pair of
+// barriers instead of W; sh holds W * NT / 64 doubles. Results valid in thread 0.
+template <int W>
+__device__ __forceinline__ void block_sums(double (&v)[W], double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[k] += __shfl_down(v[k], o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < W; ++k) sh[k * (NT / 64) + w] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      double t = 0.0;
+      for (int i = 0; i < NT / 64; ++i) t += sh[k * (NT / 64) + i];
+      v[k] = t;
+    }
 }
 
 // Fixed-order sum over nb partial rows (stride w) of column c, by the whole block; result in
@@ -47,8 +72,9 @@ __device__ __forceinline__ void sum_partials_all(const double* partials, int nb,
   for (int b = threadIdx.x; b < nb; b += NT)
 #pragma unroll
     for (int k = 0; k < W; ++k) v[k] += partials[b * W + k];
+  block_sums<W>(v, sh);
 #pragma unroll
-  for (int k = 0; k < W; ++k) out[k] = block_sum(v[k], sh);
+  for (int k = 0; k < W; ++k) out[k] = v[k];
 }
 
 int red_blocks(int64_t n) {
@@ -196,7 +222,7 @@ __global__ void k_symmetrize(double* A, int64_t n) {
 
 // ---- energy of (HW, SW): Eq. 8 -----------------------------------------------------------------
 __device__ __forceinline__ void b_energy_partials(const double* HW, const double* SW, int M, double* partials, int bid, int nb) {
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[SH_SUMS];
   const int64_t n = (int64_t)M * M;
   double tr = 0.0, f = 0.0, trs = 0.0;
   for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n; i += (int64_t)nb * NT) {
@@ -205,9 +231,9 @@ __device__ __forceinline__ void b_energy_partials(const double* HW, const double
     f += s * h;
     if (r == c) { tr += h; trs += s; }
   }
-  double a = block_sum(tr, sh);
-  double b = block_sum(f, sh);
-  double c = block_sum(trs, sh);
+  double v3[3] = {tr, f, trs};
+  block_sums<3>(v3, sh);
+  const double a = v3[0], b = v3[1], c = v3[2];
   if (threadIdx.x == 0) {
     partials[bid * 3 + 0] = a;
     partials[bid * 3 + 1] = b;
@@ -220,7 +246,7 @@ __global__ void k_energy_partials(const double* HW, const double* SW, int M, dou
 }
 
 __device__ __forceinline__ void f_energy_init_final(const double* partials, int nb, DevState* st, double* trace) {
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[SH_SUMS];
   const double tr = sum_partials(partials, nb, 3, 0, sh);
   const double f = sum_partials(partials, nb, 3, 1, sh);
   if (threadIdx.x != 0) return;
@@ -240,15 +266,16 @@ template <typename T, typename TP = T>
 __device__ __forceinline__ void b_pr_partials(const T* G, const TP* PG, const T* Gp, int64_t n, int first,
                               double* partials, const DevState* st, int bid, int nb) {
   if (st->done) return;
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[SH_SUMS];
   double s1 = 0.0, s2 = 0.0;
   for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n; i += (int64_t)nb * NT) {
     const double pg = (double)PG[i];
     s1 += pg * (double)G[i];
     if (!first) s2 += pg * (double)Gp[i];
   }
-  double a = block_sum(s1, sh);
-  double b = block_sum(s2, sh);
+  double v2[2] = {s1, s2};
+  block_sums<2>(v2, sh);
+  const double a = v2[0], b = v2[1];
   if (threadIdx.x == 0) {
     partials[bid * 2 + 0] = a;
     partials[bid * 2 + 1] = b;
@@ -269,7 +296,7 @@ __global__ void k_pr_partials4(const TG* G, const TP* PG, const TG* Gp, int64_t 
   if (st->done) return;
   typedef TG G4 __attribute__((ext_vector_type(4)));
   typedef TP P4 __attribute__((ext_vector_type(4)));
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[SH_SUMS];
   const int64_t n4 = n / 4, stride = (int64_t)gridDim.x * NT;
   const G4* g4 = reinterpret_cast<const G4*>(G);
   const G4* q4 = reinterpret_cast<const G4*>(Gp);
@@ -301,8 +328,9 @@ __global__ void k_pr_partials4(const TG* G, const TP* PG, const TG* Gp, int64_t 
       s1 += (double)PG[j] * (double)G[j];
       if (!first) s2 += (double)PG[j] * (double)Gp[j];
     }
-  double a = block_sum(s1, sh);
-  double b = block_sum(s2, sh);
+  double v2[2] = {s1, s2};
+  block_sums<2>(v2, sh);
+  const double a = v2[0], b = v2[1];
   if (threadIdx.x == 0) {
     partials[blockIdx.x * 2 + 0] = a;
     partials[blockIdx.x * 2 + 1] = b;
@@ -311,9 +339,10 @@ __global__ void k_pr_partials4(const TG* G, const TP* PG, const TG* Gp, int64_t 
 
 __device__ __forceinline__ void f_pr_final(const double* partials, int nb, int first, DevState* st) {
   if (st->done) return;
-  __shared__ double sh[NT / 64];
-  const double s1 = sum_partials(partials, nb, 2, 0, sh);
-  const double s2 = sum_partials(partials, nb, 2, 1, sh);
+  __shared__ double sh[SH_SUMS];
+  double s2v[2];
+  sum_partials_all<2>(partials, nb, sh, s2v);
+  const double s1 = s2v[0], s2 = s2v[1];
   if (threadIdx.x != 0) return;
   double beta = 0.0;
   if (!first) {
@@ -435,7 +464,7 @@ __device__ __forceinline__ void b_coef_partials(const double* HW, const double* 
                                 double* partials, const DevState* st, int bid, int nb) {
   if (st->done) return;
   __shared__ double t[32][33];
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[SH_SUMS];
   double acc[NCOEF];
 #pragma unroll
   for (int k = 0; k < NCOEF; ++k) acc[k] = 0.0;
@@ -470,10 +499,9 @@ __device__ __forceinline__ void b_coef_partials(const double* HW, const double* 
       }
     }
   }
-  for (int k = 0; k < NCOEF; ++k) {
-    const double v = block_sum(acc[k], sh);
-    if (threadIdx.x == 0) partials[bid * NCOEF + k] = v;
-  }
+  block_sums<NCOEF>(acc, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NCOEF; ++k) partials[bid * NCOEF + k] = acc[k];
 }
 
 __global__ void k_coef_partials(const double* HW, const double* SW, const double* H1,
@@ -561,7 +589,7 @@ __device__ int line_minimum(const double* a, double* xout) {
 
 __device__ __forceinline__ void f_line_final(const double* partials, int nb, DevState* st) {
   if (st->done) return;
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[SH_SUMS];
   double s[NCOEF];
   sum_partials_all<NCOEF>(partials, nb, sh, s);
   if (threadIdx.x != 0) return;
@@ -791,7 +819,7 @@ __device__ __forceinline__ void b_update_mm(double* HW, double* SW, const double
                             const DevState* st, int bid, int nb) {
   if (st->done) return;
   __shared__ double th[32][33], ts[32][33];
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[SH_SUMS];
   const double x = st->x;
   double tr = 0.0, f = 0.0, trs = 0.0;
   const int tb = (M + 31) / 32;
@@ -820,9 +848,9 @@ __device__ __forceinline__ void b_update_mm(double* HW, double* SW, const double
       }
     }
   }
-  const double a = block_sum(tr, sh);
-  const double b = block_sum(f, sh);
-  const double c = block_sum(trs, sh);
+  double v3[3] = {tr, f, trs};
+  block_sums<3>(v3, sh);
+  const double a = v3[0], b = v3[1], c = v3[2];
   if (threadIdx.x == 0) {
     partials[bid * 3 + 0] = a;
     partials[bid * 3 + 1] = b;
@@ -841,7 +869,7 @@ __global__ __launch_bounds__(NT) void k_update_mm_sym(double* HW, double* SW, co
                                                       const DevState* st) {
   if (st->done) return;
   __shared__ double th[32][33], ts[32][33], oh[32][33], os[32][33];
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[SH_SUMS];
   const double x = st->x;
   double tr = 0.0, f = 0.0, trs = 0.0;
   const int T = (M + 31) / 32;
@@ -895,9 +923,9 @@ __global__ __launch_bounds__(NT) void k_update_mm_sym(double* HW, double* SW, co
       }
     }
   }
-  const double a = block_sum(tr, sh);
-  const double b = block_sum(f, sh);
-  const double c = block_sum(trs, sh);
+  double v3[3] = {tr, f, trs};
+  block_sums<3>(v3, sh);
+  const double a = v3[0], b = v3[1], c = v3[2];
   if (threadIdx.x == 0) {
     partials[blockIdx.x * 3 + 0] = a;
     partials[blockIdx.x * 3 + 1] = b;
@@ -908,10 +936,10 @@ __global__ __launch_bounds__(NT) void k_update_mm_sym(double* HW, double* SW, co
 __device__ __forceinline__ void f_update_final(const double* partials, int nb, int M, DevState* st,
                                double* trace) {
   if (st->done) return;
-  __shared__ double sh[NT / 64];
-  const double tr = sum_partials(partials, nb, 3, 0, sh);
-  const double f = sum_partials(partials, nb, 3, 1, sh);
-  const double trs = sum_partials(partials, nb, 3, 2, sh);
+  __shared__ double sh[SH_SUMS];
+  double s3[3];
+  sum_partials_all<3>(partials, nb, sh, s3);
+  const double tr = s3[0], f = s3[1], trs = s3[2];
   if (threadIdx.x != 0) return;
   const double E_new = 4.0 * tr - 2.0 * f;
   const double E_old = st->E;
