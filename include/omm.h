@@ -118,7 +118,8 @@ int omm_set_stream(omm_ctx *ctx, void *hip_stream);
 /* Hamiltonian, overlap and (nullable) kinetic matrices of the generalized eigenproblem
  * H c = eps S c (Sec. 2.1, Eq. 1). Host pointers, N*N each, copied in. T is needed only for a
  * finite tau > 0 (Eq. 17). Checked for finite values and symmetry (relative 1e-10):
- * OMM_E_NONFINITE / OMM_E_ASYMMETRIC (the previous inputs then stay). Ends the active
+ * OMM_E_NONFINITE / OMM_E_ASYMMETRIC (the previous inputs then stay; a HIP failure while copying
+ * leaves the context without inputs, OMM_E_STATE until the next successful call). Ends the active
  * minimization and drops the cached shift Hs = H - eta S and everything derived from it. When
  * S and T are bit for bit those of the previous call (an SCF step at a fixed geometry, Sec. 3),
  * what derives from them alone is kept: the preconditioner P, the Cholesky factor of the

@@ -597,6 +597,11 @@ int omm_batch_set_HS(omm_batch* b, int i, const double* H, const double* S, cons
   // stored copies: when neither changed bit for bit (an SCF step at a fixed geometry) the
   // system keeps its preconditioner.
   const bool compare = s.have_HS && (T != nullptr) == s.have_T;
+  const int kept_kind = s.p_kind;
+  // until the new inputs are all in: a failure below leaves the system without inputs and
+  // without a preconditioner
+  s.have_HS = false;
+  s.p_kind = -1;
   int diff = compare ? 0 : 1;
   BHIP(b, hipMemcpyAsync(b->d_cmp, &diff, sizeof(int), hipMemcpyHostToDevice, b->stream));
   double* dsts[2] = {s.S, s.T};
@@ -613,7 +618,7 @@ int omm_batch_set_HS(omm_batch* b, int i, const double* H, const double* S, cons
   BHIP(b, hipStreamSynchronize(b->stream));
   s.have_T = T != nullptr;
   s.have_HS = true;
-  if (diff) s.p_kind = -1;
+  if (!diff) s.p_kind = kept_kind;
   drop_graph(b);
   return OMM_OK;
 }

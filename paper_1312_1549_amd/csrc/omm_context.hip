@@ -1532,6 +1532,7 @@ int load_S_T(omm_ctx* c, const double* src_S, const double* src_T, bool host, bo
   const int64_t n = c->N;
   const size_t nn = (size_t)n * n, bytes = nn * sizeof(double);
   const bool compare = c->have_HS && (src_T != nullptr) == c->have_T;
+  c->have_HS = false;  // until the new inputs are all in
   if (src_T) TRY(dalloc(c, &c->T, nn));
   TRY(dalloc(c, &c->flags, 8));
   TRY(dalloc(c, &c->Hs, nn));
@@ -1554,6 +1555,30 @@ int load_S_T(omm_ctx* c, const double* src_S, const double* src_T, bool host, bo
   return OMM_OK;
 }
 
+// S and T (compared with the stored copies), then H, from host or device memory. On failure the
+// inputs count as absent and everything derived from them is dropped.
+int load_inputs(omm_ctx* c, const double* H, const double* S, const double* T, bool host) {
+  const size_t bytes = (size_t)c->N * c->N * sizeof(double);
+  bool st_changed = true;
+  int r = load_S_T(c, S, T, host, &st_changed);
+  if (r == OMM_OK) {
+    const hipError_t e0 = hipMemcpyAsync(c->H, H, bytes,
+                                         host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                                         c->stream);
+    const hipError_t e1 = e0 == hipSuccess ? symmetrize(c->H, c->N, c->stream) : e0;
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(c->stream) : e1;
+    if (e2 != hipSuccess) r = fail(c, OMM_E_HIP, std::string("copying H: ") + hipGetErrorString(e2));
+  }
+  if (r != OMM_OK) {
+    invalidate(c, true);
+    return r;
+  }
+  c->have_T = T != nullptr;
+  c->have_HS = true;
+  invalidate(c, st_changed);
+  return OMM_OK;
+}
+
 int omm_set_HS(omm_ctx* c, const double* H, const double* S, const double* T) {
   if (!c) return OMM_E_ARG;
   if (!H || !S) return fail(c, OMM_E_ARG, "H and S are required");
@@ -1569,18 +1594,9 @@ int omm_set_HS(omm_ctx* c, const double* H, const double* S, const double* T) {
     }
   }
   TRY(ensure_inputs(c));
-  const size_t bytes = (size_t)n * n * sizeof(double);
   // Validated to 1e-10; store exactly symmetric copies so that every operator product may read
   // rows in place of columns.
-  bool st_changed = true;
-  TRY(load_S_T(c, S, T, true, &st_changed));
-  HIPCHK(c, hipMemcpyAsync(c->H, H, bytes, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, symmetrize(c->H, n, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->have_T = T != nullptr;
-  c->have_HS = true;
-  invalidate(c, st_changed);
-  return OMM_OK;
+  return load_inputs(c, H, S, T, true);
 }
 
 int omm_set_HS_device(omm_ctx* c, const double* dH, const double* dS, const double* dT) {
@@ -1601,16 +1617,7 @@ int omm_set_HS_device(omm_ctx* c, const double* dH, const double* dS, const doub
     if (h[0]) return fail(c, OMM_E_NONFINITE, std::string(names[i]) + " has a non-finite entry");
     if (h[1]) return fail(c, OMM_E_ASYMMETRIC, std::string(names[i]) + " is not symmetric");
   }
-  const size_t bytes = (size_t)n * n * sizeof(double);
-  bool st_changed = true;
-  TRY(load_S_T(c, dS, dT, false, &st_changed));
-  HIPCHK(c, hipMemcpyAsync(c->H, dH, bytes, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, symmetrize(c->H, n, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->have_T = dT != nullptr;
-  c->have_HS = true;
-  invalidate(c, st_changed);
-  return OMM_OK;
+  return load_inputs(c, dH, dS, dT, false);
 }
 
 int omm_minimize(omm_ctx* c, const double* C0, double eta, double tau, double tol, int max_iter) {

@@ -247,17 +247,23 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def test_new_H_keeps_the_preconditioner_new_S_or_T_rebuilds_it(lib_ok, c1):
+@pytest.mark.parametrize("inputs", ["host", "device"])
+def test_new_H_keeps_the_preconditioner_new_S_or_T_rebuilds_it(lib_ok, c1, inputs):
     """SCF reuse (Sec. 3: the next SCF step starts from the previous coefficients): omm_set_HS
-    with a new H but the same S and T keeps P = (S + T/tau)^-1 (Sec. 2.4, Eq. 17), which stays
-    readable before the next minimization; a new S or T drops it, and the next minimization
-    builds the inverse of the new S + T/tau. Every minimum matches its closed form."""
+    (omm_set_HS_device for device inputs) with a new H but the same S and T keeps
+    P = (S + T/tau)^-1 (Sec. 2.4, Eq. 17), which stays readable before the next minimization;
+    a new S or T drops it, and the next minimization builds the inverse of the new S + T/tau.
+    Every minimum matches its closed form."""
+    import torch
     from paper_1312_1549_amd import OMMError
 
     s, C0, w = c1
     eta, tau = 0.5, 10.0
-    _say("set_HS reuse of P, c1 fp64")
+    _say(f"set_HS reuse of P, c1 fp64, {inputs} inputs")
     solver = lib_ok(s.N, s.M, precision="fp64")
+    if inputs == "device":
+        set_HS = solver.set_HS
+        solver.set_HS = lambda *m: set_HS(*(torch.from_numpy(x).cuda() for x in m))
 
     def run(H, S, T):
         solver.minimize(C0, eta=eta, tau=tau, tol=1e-14, max_iter=5000)
