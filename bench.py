@@ -81,11 +81,13 @@ def measured_traffic(workload, precision):
 
 
 def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=False, resync=20,
-                    flavour="dense", sparse=False, per_step=1):
+                    flavour="dense", sparse=False, per_step=1, step_walls=None):
     """Wall time of `steps` steps of `per_step` line searches each, after `warmup` steps. With the
     mixed scheme (refine) per_step is the resynchronization interval, so the window holds whole
     periods; the run restarts from C0 after the warm-up (setup outside the window) and the
-    window's resynchronizations are counted from the scheme's checkpoints."""
+    window's resynchronizations are counted from the scheme's checkpoints. With `step_walls` (a
+    list) the window runs step by step, each step's wall time appended (same line searches: the
+    resynchronization schedule counts across calls)."""
     solver = OMM(s.N, s.M, precision=prec, refine=refine, resync=resync, flavour=flavour,
                  sparse=sparse)
     solver.set_HS(dev["H"], dev["S"], dev["T"])
@@ -98,7 +100,14 @@ def time_iterations(OMM, torch, dev, s, prec, steps, warmup, prof_steps, refine=
     solver.minimize(dev["C0"], eta=s.eta, tau=s.tau, tol=0.0, max_iter=0)  # restart from C0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    solver.iterate(steps * per_step)
+    if step_walls is None:
+        solver.iterate(steps * per_step)
+    else:
+        for _ in range(steps):
+            ts = time.perf_counter()
+            solver.iterate(per_step)
+            torch.cuda.synchronize()
+            step_walls.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     resyncs = None
@@ -530,10 +539,12 @@ def main():
     R = args.resync if mixed else 1  # line searches per step
     side = max(2, args.steps // 4)   # steps of the flavours timed beside the headline
     log(f"timing {args.precision}: warmup {args.warmup}, steps {args.steps} x {R} line searches")
+    step_walls = []
     wall, setup_s, stages, resyncs = time_iterations(
         OMM, torch, dev, s, args.precision, args.steps, args.warmup, prof_steps, refine=mixed,
-        resync=args.resync, per_step=R)
+        resync=args.resync, per_step=R, step_walls=step_walls)
     ips = args.steps * R / wall
+    step_rates = sorted(R / w for w in step_walls)
     log(f"{args.precision}: {ips:.3f} iters/s ({1e3 * wall / (args.steps * R):.3f} ms/line search,"
         f" {resyncs} resynchronizations in the window)")
     rates = {}
@@ -611,6 +622,10 @@ def main():
     }
     if mixed:
         result["resyncs_in_window"] = resyncs
+    # spread of the window: the rate of each step (one resynchronization period in the BF16
+    # scheme), median, lowest and highest
+    result["step_rates"] = {"median": step_rates[len(step_rates) // 2], "min": step_rates[0],
+                            "max": step_rates[-1], "unit": "iters/s", "steps": len(step_rates)}
     result.update(rates)
     if chol:
         result["cholesky_flavour"] = chol
