@@ -165,6 +165,51 @@ def time_to_converged(OMM, torch, dev, s, prec, E_ref, target, max_iter, resync,
     return out
 
 
+def c2_grid_bench(args, torch):
+    """The 2048-orbital workload (N = 2048, M = 384) over the shift x preconditioner grid
+    eta in {0, 0.5} x tau in {1, 10, 100}, per precision: line searches to the stopping rule,
+    wall time from omm_minimize entry (P built and tiles tuned by an untimed first call), rate,
+    and the error against the closed form of each eta (tests/golden/c2_reference.json). FP64 and
+    FP32 products with FP64 refinement run to tol 1e-12, the BF16 scheme on an FP64 state to
+    tol 1e-10 at its resynchronizations."""
+    from paper_1312_1549_amd import OMM
+    from synth import config_system, start_coefficients
+
+    s = config_system("c2", 0)
+    C0 = start_coefficients(s.S, s.M, 1)
+    ref = json.loads((ROOT / "tests" / "golden" / "c2_reference.json").read_text())
+    E_ref = ref.get("E_min_by_eta", {}) if ref.get("trace_H") and abs(
+        ref["trace_H"] - float(np.trace(s.H))) <= 1e-9 * abs(ref["trace_H"]) else {}
+    dev = {k: torch.from_numpy(v).cuda() for k, v in (("H", s.H), ("S", s.S), ("T", s.T),
+                                                      ("C0", C0))}
+    rows = []
+    for prec, refine, tol in (("fp64", False, 1e-12), ("fp32", True, 1e-12),
+                              ("bf16x3", True, 1e-10)):
+        for eta in (0.0, 0.5):
+            for tau in (1.0, 10.0, 100.0):
+                solver = OMM(s.N, s.M, precision=prec, refine=refine, resync=args.resync)
+                solver.set_HS(dev["H"], dev["S"], dev["T"])
+                solver.minimize(dev["C0"], eta=eta, tau=tau, tol=0.0, max_iter=2)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = solver.minimize(dev["C0"], eta=eta, tau=tau, tol=tol, max_iter=6000)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                it = int(solver.stats()[0])
+                E = solver.energy()
+                row = {"precision": prec + ("+fp64" if refine else ""), "eta": eta, "tau": tau,
+                       "tol": tol, "status": int(st), "line_searches": it, "s": wall,
+                       "iters_per_s": it / wall, "E": E}
+                if str(eta) in E_ref:
+                    row["rel_err_vs_closed_form"] = abs(E - E_ref[str(eta)]) / abs(E_ref[str(eta)])
+                rows.append(row)
+                solver.close()
+                log(f"c2 grid {row['precision']} eta={eta} tau={tau}: {it} line searches, "
+                    f"{wall:.2f}s, rel err {row.get('rel_err_vs_closed_form', float('nan')):.2e}")
+    return {"workload": WORKLOADS["c2"].split(", eta")[0] + ", eta in {0, 0.5} x tau in {1, 10, 100}",
+            "runs": rows}
+
+
 def complex_bench(args, torch):
     """Complex Hermitian problems (k-points) through OMMComplex / OMMBatchComplex: the 1024-atom
     16x8x8 lattice (4 orbitals per atom) made periodic along x at k = 0.3 (complex N = 4096,
@@ -502,6 +547,8 @@ def main():
     ap.add_argument("--no-complex", action="store_true",
                     help="skip the complex Hermitian (k-point) rates and time to converged")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batch")
+    ap.add_argument("--no-c2-grid", action="store_true",
+                    help="skip the eta x tau grid of the 2048-orbital workload")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline scheme only (profiling runs): implies every --no-* "
                          "flag and skips the side rates and the latency workload")
@@ -512,7 +559,7 @@ def main():
     args = ap.parse_args()
     if args.only_headline:
         for flag in ("no_converge", "no_cpu_baseline", "no_fp64", "no_cholesky", "no_sparse",
-                     "no_complex", "no_batched"):
+                     "no_complex", "no_batched", "no_c2_grid"):
             setattr(args, flag, True)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -679,6 +726,9 @@ def main():
 
     if not args.no_complex and args.workload == "c3":
         result["complex_kpoints"] = complex_bench(args, torch)
+    if not args.no_c2_grid and args.workload == "c3":
+        log("c2 grid: eta x tau on the 2048-orbital workload")
+        result["c2_grid"] = c2_grid_bench(args, torch)
 
     if not args.no_batched and args.workload == "c3":
         result["batched"] = batched_bench(args)

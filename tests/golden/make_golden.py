@@ -60,7 +60,10 @@ def main(names):
         E = brute.closed_form_energy(w, s.M, s.eta)
         out = {
             "workload": name, "N": s.N, "M": s.M, "eta": s.eta, "tau": s.tau, "seed": 0,
-            "E_min": E, "eps_M": float(w[s.M - 1]), "eps_M1": float(w[s.M]),
+            "E_min": E,
+            # the same closed form at both shifts of the eta grid (below and above eps_M)
+            "E_min_by_eta": {str(e): brute.closed_form_energy(w, s.M, e) for e in (0.0, 0.5)},
+            "eps_M": float(w[s.M - 1]), "eps_M1": float(w[s.M]),
             "gap": float(w[s.M] - w[s.M - 1]), "eps_1": float(w[0]),
             "trace_H": float(np.real(np.trace(s.H))), "sum_S": float(np.real(np.sum(s.S))),
             "shift": s.shift,
