@@ -256,6 +256,11 @@ int omm_batch_phase_iterations(omm_batch *b, int *iters32, int *iters64);
 /* System i: host H, S, T (N_i*N_i each; T nullable as for omm_set_HS). The system keeps its
  * preconditioner when S and T are bit for bit those of its previous call. */
 int omm_batch_set_HS(omm_batch *b, int i, const double *H, const double *S, const double *T);
+/* Same with device pointers, validated on the device (OMM_E_NONFINITE / OMM_E_ASYMMETRIC), then
+ * copied device-to-device on the batch's own stream: the caller's writes to them must be
+ * complete before the call; they are no longer read when it returns. */
+int omm_batch_set_HS_device(omm_batch *b, int i, const double *dH, const double *dS,
+                            const double *dT);
 /* C0[i]: host M_i*N_i start of system i (NULL entry: resume from its current C). eta, tau:
  * arrays of nsys values; max_iter bounds each phase. Returns OMM_OK if every system converged,
  * OMM_W_MAXITER if some did not, or the first error. */

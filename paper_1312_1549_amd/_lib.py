@@ -59,6 +59,7 @@ PROTOTYPES = {
     "omm_batch_create": (ct.c_int, [ct.c_int, _c_i64_p, _c_i64_p, ct.POINTER(_vp)]),
     "omm_batch_destroy": (ct.c_int, [_vp]),
     "omm_batch_set_HS": (ct.c_int, [_vp, ct.c_int, _vp, _vp, _vp]),
+    "omm_batch_set_HS_device": (ct.c_int, [_vp, ct.c_int, _vp, _vp, _vp]),
     "omm_batch_minimize": (ct.c_int, [_vp, ct.POINTER(_vp), _c_double_p, _c_double_p,
                                       ct.c_double, ct.c_int]),
     "omm_batch_energy": (ct.c_int, [_vp, _c_double_p]),

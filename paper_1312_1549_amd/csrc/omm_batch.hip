@@ -78,7 +78,8 @@ struct omm_batch {
   SysDev* d_sys64 = nullptr;    // FP64 phase
   double* inv_work = nullptr;
   size_t inv_cap = 0;
-  int* d_cmp = nullptr;  // change flag of omm_batch_set_HS's S / T comparison
+  int* d_cmp = nullptr;  // change flag of omm_batch_set_HS's S / T comparison, then the two
+                         // flags (non-finite, asymmetric) of the device-input validation
   PhaseLists L32, L64;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -573,25 +574,41 @@ int omm_batch_destroy(omm_batch* b) {
   return OMM_OK;
 }
 
-int omm_batch_set_HS(omm_batch* b, int i, const double* H, const double* S, const double* T) {
+namespace {
+// omm_batch_set_HS and omm_batch_set_HS_device: validation (on the host, or by a kernel for
+// device inputs), then S and T compared with the stored copies, then H.
+int batch_set_HS(omm_batch* b, int i, const double* H, const double* S, const double* T,
+                 bool host) {
   if (!b) return OMM_E_ARG;
   if (i < 0 || i >= (int)b->sys.size()) return bfail(b, OMM_E_ARG, "system index out of range");
   if (!H || !S) return bfail(b, OMM_E_ARG, "H and S are required");
   BSys& s = b->sys[i];
   const int64_t n = s.N;
+  const size_t nn = (size_t)n * n;
+  BTRY(balloc(b, &b->d_cmp, 2));
   const double* mats[3] = {H, S, T};
   for (int k = 0; k < 3; ++k) {
     if (!mats[k]) continue;
-    bool fin = true;
-    if (!host_symmetric(mats[k], n, &fin))
+    bool fin = true, sym = true;
+    if (host) {
+      sym = host_symmetric(mats[k], n, &fin);
+    } else {
+      int h[2] = {0, 0};
+      BHIP(b, hipMemsetAsync(b->d_cmp, 0, 2 * sizeof(int), b->stream));
+      BHIP(b, validate_symmetric(mats[k], n, 1e-10, b->d_cmp, b->stream));
+      BHIP(b, hipMemcpyAsync(h, b->d_cmp, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+      BHIP(b, hipStreamSynchronize(b->stream));
+      fin = h[0] == 0;
+      sym = fin && h[1] == 0;
+    }
+    if (!sym)
       return bfail(b, fin ? OMM_E_ASYMMETRIC : OMM_E_NONFINITE,
                    "system " + std::to_string(i) + ": input not finite/symmetric");
   }
-  const size_t nn = (size_t)n * n;
+  const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
   BTRY(balloc(b, &s.H, nn));
   BTRY(balloc(b, &s.S, nn));
   BTRY(balloc(b, &s.Hs64, nn));
-  BTRY(balloc(b, &b->d_cmp, 1));
   if (T) BTRY(balloc(b, &s.T, nn));
   // S and T go in through Hs (rebuilt from H and S by the next setup) and are compared with the
   // stored copies: when neither changed bit for bit (an SCF step at a fixed geometry) the
@@ -608,12 +625,12 @@ int omm_batch_set_HS(omm_batch* b, int i, const double* H, const double* S, cons
   const double* srcs[2] = {S, T};
   for (int k = 0; k < 2; ++k) {
     if (!srcs[k]) continue;
-    BHIP(b, hipMemcpyAsync(s.Hs64, srcs[k], nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(s.Hs64, srcs[k], nn * sizeof(double), kind, b->stream));
     BHIP(b, symmetrize(s.Hs64, n, b->stream));
     BHIP(b, copy_compare_f64(s.Hs64, dsts[k], (int64_t)nn, b->d_cmp, b->stream));
   }
   BHIP(b, hipMemcpyAsync(&diff, b->d_cmp, sizeof(int), hipMemcpyDeviceToHost, b->stream));
-  BHIP(b, hipMemcpyAsync(s.H, H, nn * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(s.H, H, nn * sizeof(double), kind, b->stream));
   BHIP(b, symmetrize(s.H, n, b->stream));
   BHIP(b, hipStreamSynchronize(b->stream));
   s.have_T = T != nullptr;
@@ -621,6 +638,16 @@ int omm_batch_set_HS(omm_batch* b, int i, const double* H, const double* S, cons
   if (!diff) s.p_kind = kept_kind;
   drop_graph(b);
   return OMM_OK;
+}
+}  // namespace
+
+int omm_batch_set_HS(omm_batch* b, int i, const double* H, const double* S, const double* T) {
+  return batch_set_HS(b, i, H, S, T, true);
+}
+
+int omm_batch_set_HS_device(omm_batch* b, int i, const double* dH, const double* dS,
+                            const double* dT) {
+  return batch_set_HS(b, i, dH, dS, dT, false);
 }
 
 int omm_batch_set_precision(omm_batch* b, int mode, int fp64_refine) {

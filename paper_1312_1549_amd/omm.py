@@ -353,8 +353,16 @@ class OMMBatch:
 
     def set_HS(self, i: int, H, S, T=None):
         n = (self.Ns[i], self.Ns[i])
-        self._check(self._L.omm_batch_set_HS(self._h, i, _host_ptr(H, n), _host_ptr(S, n),
-                                             _host_ptr(T, n) if T is not None else None))
+        if _is_torch(H):
+            import torch
+
+            # the batch copies on its own stream: the producers of H, S, T must have finished
+            torch.cuda.current_stream().synchronize()
+            self._check(self._L.omm_batch_set_HS_device(
+                self._h, i, _dev_ptr(H, n), _dev_ptr(S, n), _dev_ptr(T, n) if T is not None else None))
+        else:
+            self._check(self._L.omm_batch_set_HS(self._h, i, _host_ptr(H, n), _host_ptr(S, n),
+                                                 _host_ptr(T, n) if T is not None else None))
 
     def minimize(self, C0s, etas, taus, tol: float, max_iter: int) -> int:
         k = len(self.Ns)

@@ -119,3 +119,47 @@ def test_batch_precision_arguments_are_checked(torch):
         b.set_precision("bf16x3", True)
     assert e.value.code == -1
     b.close()
+
+
+def test_device_inputs_match_host_inputs(torch, systems):
+    """omm_batch_set_HS_device: the same systems handed over as CUDA tensors give bit for bit the
+    energies and line-search counts of host inputs; device inputs are validated on the device
+    (an asymmetric H or a non-finite S is refused), and a refused call leaves the system's
+    previous inputs in place."""
+    from paper_1312_1549_amd import OMMBatch, OMMError
+
+    xs, refs = systems
+    xs, refs = xs[:3], refs[:3]
+    _say("batch fp64 device inputs N=" + ",".join(str(x.N) for x in xs))
+    C0s = [start_coefficients(x.S, x.M, 3200 + i) for i, x in enumerate(xs)]
+    etas, taus = [x.eta for x in xs], [x.tau for x in xs]
+    out = []
+    for device in (False, True):
+        b = OMMBatch([x.N for x in xs], [x.M for x in xs], precision="fp64")
+        for i, x in enumerate(xs):
+            if device:
+                b.set_HS(i, *(torch.from_numpy(m).cuda() for m in (x.H, x.S, x.T)))
+            else:
+                b.set_HS(i, x.H, x.S, x.T)
+        st = b.minimize(C0s, etas, taus, 1e-13, 6000)
+        assert st == 0
+        out.append((b.energies(), b.iterations()))
+        if device:
+            x = xs[0]
+            Ha = x.H.copy()
+            Ha[0, 1] += 1e-3
+            with pytest.raises(OMMError) as e:
+                b.set_HS(0, *(torch.from_numpy(m).cuda() for m in (Ha, x.S, x.T)))
+            assert e.value.code == -9
+            Sn = x.S.copy()
+            Sn[2, 2] = np.nan
+            with pytest.raises(OMMError) as e:
+                b.set_HS(0, *(torch.from_numpy(m).cuda() for m in (x.H, Sn, x.T)))
+            assert e.value.code == -5
+            # the refused calls changed nothing: the same minimum again
+            assert b.minimize(C0s, etas, taus, 1e-13, 6000) == 0
+            assert np.array_equal(b.energies(), out[1][0])
+        b.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.all(_errors(out[1][0], refs) <= 1e-10)
