@@ -236,6 +236,11 @@ void free_plane(Plane& p) {
 // the 64x64 tiling leaves CUs idle and K is long. The autotuner replaces it per shape.
 void heuristic_tiling(GemmDesc& d, int M, int N, int K) {
   const int cus = 256;
+  if ((d.compute == CF64 || d.compute == CF32) && (long)M * N <= 65536 && K <= 512) {
+    d.tile = 7;  // one wave per 16 x 16 tile, no staging: a few launches' latency, not a K loop's
+    d.splitk = 1;
+    return;
+  }
   const long t128 = (long)((M + 127) / 128) * ((N + 127) / 128);
   const long t64 = (long)((M + 63) / 64) * ((N + 63) / 64);
   d.tile = t128 >= cus ? 0 : 1;

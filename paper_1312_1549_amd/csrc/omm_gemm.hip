@@ -107,6 +107,7 @@ sk_fn pick_sk(const GemmDesc& d) {
 bool gemm_supported(const GemmDesc& d) {
   if (d.tile < 0 || d.tile >= NTILES) return false;
   if (d.tile == 6) return d.splitk <= 1 && pick_sk(d) != nullptr;
+  if (d.tile == 7 && d.splitk > 1) return false;
   if (d.compute == CF64) return pick_f64(d) != nullptr;
   if (d.compute == CF32) return pick_f32(d) != nullptr;
   if (d.compute == CBF16X3) return pick_bf16x3(d) != nullptr;

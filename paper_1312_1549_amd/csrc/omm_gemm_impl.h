@@ -1081,6 +1081,53 @@ __global__ __launch_bounds__(WM* WN * 64, MINW) void gemm_kernel(GemmBatch batch
                                                                   ws, blockIdx.z, gridDim.z);
 }
 
+// Tiny products (FP64 and FP32 modes, a few hundred outputs a side, K of a few hundred): one wave
+// per 16 x 16 output tile, operands read from memory straight into MFMA fragments (lane l holds
+// A(i0 + l % 16, k + l / 16) and B(k + l / 16, j0 + l % 16)), the loads of KU 4-deep K steps
+// issued before their MFMAs. A staged macro tile spends such a product waiting on its K loop.
+template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB>
+__global__ __launch_bounds__(64) void gemm_kernel_tiny(GemmBatch batch, const int* done,
+                                                       int nsplit, double* ws) {
+  static_assert(MODE == CF64 || MODE == CF32, "FP64 / FP32 MFMA fragments");
+  typedef typename AccT<MODE>::type acc_t;
+  typedef typename std::conditional<MODE == CF64, double, float>::type mt;
+  if (done && *done) return;
+  const GemmOp& op = batch.op[blockIdx.z];
+  const int tiles_m = (op.M + 15) / 16, tiles_n = (op.N + 15) / 16;
+  int tm, tn;
+  if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
+  if (op.tri && tm > tn) return;  // mirrored afterwards
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+  const int i = tm * 16 + li, j = tn * 16 + li;
+  acc_t acc[1][1];
+  acc[0][0] = acc_t{0, 0, 0, 0};
+  constexpr int KU = 32;
+  for (int seg = 0; seg < op.nseg; ++seg) {
+    const TA* A = static_cast<const TA*>(op.A[seg]);
+    const TB* B = static_cast<const TB*>(op.B[seg]);
+    const int64_t lda = op.lda[seg], ldb = op.ldb[seg];
+    const int K = op.K[seg];
+    for (int k0 = 0; k0 < K; k0 += 4 * KU) {
+      mt a[KU], b[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + 4 * u + lk;
+        const bool kin = k < K;
+        a[u] = kin && i < op.M
+                   ? (mt)(LA == KC ? A[(int64_t)i * lda + k] : A[(int64_t)k * lda + i])
+                   : (mt)0;
+        b[u] = kin && j < op.N
+                   ? (mt)(LB == KC ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j])
+                   : (mt)0;
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u) acc[0][0] = mfma4(a[u], b[u], acc[0][0]);
+    }
+  }
+  store_acc<MODE, TC, TX, 1, 1>(op, acc, tm * 16, tn * 16, lane, 0, 1, ws, blockIdx.z,
+                                gridDim.z);
+}
+
 // Grouped products of uneven shapes: a persistent grid walks the concatenated tile list of all
 // ops (tile_start = prefix sums); an op whose `done` flag is set is skipped.
 struct GroupedArgs {
@@ -1128,17 +1175,19 @@ sk_fn pick_sk_kernel() {
 // two-product modes, 2 for BF16x3).
 //    6: tile 5 on a stream-K schedule (persistent, whole-tile rounds, then the remaining tiles
 //       cut evenly across the workgroups).
-constexpr int NTILES = 7;
+//    7: FP64 / FP32 only: 16 x 16, one wave per tile, fragments loaded from memory
+//       (gemm_kernel_tiny), no split-K.
+constexpr int NTILES = 8;
 constexpr int NTILES_GROUPED = 5;
 inline bool tile_big(int t, int mode) { return t >= 4 && is_bf16_mode(mode); }
 inline int tile_bm(int t, int mode) {
-  return t == 1 ? 64 : (t == 2 || tile_big(t, mode) ? 256 : 128);
+  return t == 7 ? 16 : t == 1 ? 64 : (t == 2 || tile_big(t, mode) ? 256 : 128);
 }
 inline int tile_bn(int t, int mode) {
-  return t == 1 ? 64 : (t == 3 || tile_big(t, mode) ? 256 : 128);
+  return t == 7 ? 16 : t == 1 ? 64 : (t == 3 || tile_big(t, mode) ? 256 : 128);
 }
 inline int tile_threads(int t, int mode) {
-  return (t == 2 || t == 3 || tile_big(t, mode)) ? 512 : 256;
+  return t == 7 ? 64 : (t == 2 || t == 3 || tile_big(t, mode)) ? 512 : 256;
 }
 
 template <int MODE, typename TA, typename TB, typename TC, typename TX, int LA, int LB>
@@ -1175,6 +1224,11 @@ gemm_fn pick_tile(int tile) {
       if constexpr (is_bf16_mode(MODE) && std::is_same<TA, unsigned short>::value &&
                     std::is_same<TB, unsigned short>::value && LA == KC && LB == KC)
         return gemm_kernel_dma<MODE, TC, TX, dma_stages(MODE)>;
+      else
+        return nullptr;
+    case 7:
+      if constexpr (MODE == CF64 || MODE == CF32)
+        return gemm_kernel_tiny<MODE, TA, TB, TC, TX, LA, LB>;
       else
         return nullptr;
     default: return nullptr;

@@ -118,6 +118,31 @@ def test_fp64_ragged_shapes(lib_ok, ragged):
     np.testing.assert_allclose(tr[:30], ref.energies[:30], rtol=1e-10, atol=0)
 
 
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-11), ("fp32", 1e-5)])
+def test_tiny_tile_matches_staged_tile(lib_ok, ragged, c1, precision, rtol, monkeypatch):
+    """The one-wave 16 x 16 tile that small FP64 / FP32 products take (N = 128 and N = 200 here:
+    every product of the line search, the initial products and the outputs) against the staged
+    128 x 128 tile pinned with OMM_TILE=0: the same energies along the trajectory to rounding,
+    and for FP64 the same minimum as the closed form."""
+    for name, (s, C0, w) in (("c1", c1), ("ragged", ragged)):
+        _say(f"tiny vs staged tile {name} N={s.N} M={s.M} {precision}")
+        traces = []
+        for tile in (None, "0"):
+            if tile is None:
+                monkeypatch.delenv("OMM_TILE", raising=False)
+            else:
+                monkeypatch.setenv("OMM_TILE", tile)
+            solver, status = _run(lib_ok, s, C0, 0.5, 10.0, 1e-14 if precision == "fp64" else 1e-7,
+                                  5000, precision=precision, refine=False)
+            traces.append(solver.energy_trace())
+            if precision == "fp64":
+                E_ref = brute.closed_form_energy(w, s.M, 0.5)
+                assert abs(solver.energy() - E_ref) <= 1e-10 * abs(E_ref)
+            solver.close()
+        n = min(20, len(traces[0]), len(traces[1]))
+        np.testing.assert_allclose(traces[0][:n], traces[1][:n], rtol=rtol, atol=0)
+
+
 @pytest.mark.parametrize("tau", [10.0, math.inf])
 def test_preconditioner_matches_inverse(lib_ok, ragged, c1, tau):
     for s, C0, _ in (c1, ragged):
