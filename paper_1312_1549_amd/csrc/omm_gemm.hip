@@ -235,7 +235,8 @@ hipError_t gemm_launch(const GemmDesc& d, const GemmOp* ops, int nops, const int
     tri = true;
   }
   hipError_t e = launch_products(d, ops, nops, done, ws, ws_bytes, s);
-  if (e != hipSuccess || !tri || ops[0].M <= 0) return e;
+  // the one-wave tile writes both halves of a symmetric result itself
+  if (e != hipSuccess || !tri || ops[0].M <= 0 || d.tile == 7) return e;
   GemmBatch b;
   for (int i = 0; i < nops; ++i) b.op[i] = ops[i];
   const int nb = (ops[0].M + 31) / 32;

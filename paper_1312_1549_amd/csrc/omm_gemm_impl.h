@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(64) void gemm_kernel_tiny(GemmBatch batch, const in
   const int tiles_m = (op.M + 15) / 16, tiles_n = (op.N + 15) / 16;
   int tm, tn;
   if (!tile_of(tiles_m, tiles_n, tm, tn)) return;
-  if (op.tri && tm > tn) return;  // mirrored afterwards
+  if (op.tri && tm > tn) return;  // written by its mirror tile
   const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
   const int i = tm * 16 + li, j = tn * 16 + li;
   acc_t acc[1][1];
@@ -1123,6 +1123,22 @@ __global__ __launch_bounds__(64) void gemm_kernel_tiny(GemmBatch batch, const in
 #pragma unroll
       for (int u = 0; u < KU; ++u) acc[0][0] = mfma4(a[u], b[u], acc[0][0]);
     }
+  }
+  if (op.tri) {
+    // symmetric result: each upper element is also stored to its mirror, in place of the
+    // separate mirror pass of the staged tiles
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = MODE == CF64 ? lk + 4 * r : 4 * lk + r;
+      const int row = tm * 16 + rr, col = tn * 16 + li;
+      if (row < op.M && col < op.N && row <= col) {
+        double v = op.alpha * (double)acc[0][0][r];
+        if (op.X) v += op.beta * (double)ldg<TX>(op.X, (int64_t)row * op.ldx + col);
+        store_out<TC>(op, row, col, v);
+        if (row < col) store_out<TC>(op, col, row, v);
+      }
+    }
+    return;
   }
   store_acc<MODE, TC, TX, 1, 1>(op, acc, tm * 16, tn * 16, lane, 0, 1, ws, blockIdx.z,
                                 gridDim.z);
