@@ -330,6 +330,8 @@ int autotune(omm_ctx* c, GemmDesc d, GemmOp* ops, int nops, int K, std::pair<int
     if (!gemm_supported(dt)) continue;
     const int bm = gemm_tile_rows(t, d.compute), bn = gemm_tile_cols(t, d.compute);
     const long tiles = (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+    // the one-wave tile re-reads its operands per 16 x 16 output tile: small products only
+    if (t == 7 && (tiles > 4096 || K > 2048)) continue;
     if (tiles >= 32 || t == 1) cands.push_back({t, 1});
     for (int sk : {2, 4, 8, 16}) {
       dt.splitk = sk;
