@@ -210,6 +210,47 @@ def c2_grid_bench(args, torch):
             "runs": rows}
 
 
+def autograd_bench(args, torch):
+    """The differentiable energy on the 1024-atom workload (N = 4096, M = 768): E = min_C of the
+    functional through omm_energy (FP32 products with FP64 refinement to tol 1e-12), then
+    E.backward() (dE/dH = the density matrix, dE/dS = minus the energy-density matrix minus eta
+    times it). Forward and backward wall times after an untimed warm-up call (preconditioner,
+    tiles), the error against the closed form (tests/golden/c5_reference.json), and at the
+    minimum Tr(dE/dH S) = 2 M (S_W = I)."""
+    from paper_1312_1549_amd import OMM, omm_energy
+    from synth import config_system, start_coefficients
+
+    s = config_system("c5", 0)
+    C0 = start_coefficients(s.S, s.M, 1)
+    E_ref = reference_energy("c5", s)
+    H = torch.from_numpy(s.H).cuda().requires_grad_(True)
+    S = torch.from_numpy(s.S).cuda().requires_grad_(True)
+    T, C0d = torch.from_numpy(s.T).cuda(), torch.from_numpy(C0).cuda()
+    solver = OMM(s.N, s.M, precision="fp32", refine=True)
+    omm_energy(H, S, T, C0d, s.eta, s.tau, 1e-6, 200, solver).backward()
+    torch.cuda.synchronize()
+    H.grad = None
+    S.grad = None
+    t0 = time.perf_counter()
+    E = omm_energy(H, S, T, C0d, s.eta, s.tau, 1e-12, 6000, solver)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    E.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    tr = float((H.grad * S.detach()).sum())
+    out = {"workload": WORKLOADS["c5"] + ", fp32 products + fp64 refinement, tol 1e-12",
+           "forward_s": t_fwd, "backward_s": t_bwd, "line_searches": int(solver.stats()[0]),
+           "trace_dEdH_S_rel_err": abs(tr - 2 * s.M) / (2 * s.M)}
+    if E_ref is not None:
+        out["rel_err_vs_closed_form"] = abs(float(E.detach()) - E_ref) / abs(E_ref)
+    solver.close()
+    log(f"autograd c5: forward {t_fwd:.2f}s ({out['line_searches']} line searches), backward "
+        f"{1e3 * t_bwd:.1f} ms, rel err {out.get('rel_err_vs_closed_form', float('nan')):.2e}")
+    return out
+
+
 def complex_bench(args, torch):
     """Complex Hermitian problems (k-points) through OMMComplex / OMMBatchComplex: the 1024-atom
     16x8x8 lattice (4 orbitals per atom) made periodic along x at k = 0.3 (complex N = 4096,
@@ -549,6 +590,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batch")
     ap.add_argument("--no-c2-grid", action="store_true",
                     help="skip the eta x tau grid of the 2048-orbital workload")
+    ap.add_argument("--no-autograd", action="store_true",
+                    help="skip the differentiable energy on the 4096-orbital workload")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline scheme only (profiling runs): implies every --no-* "
                          "flag and skips the side rates and the latency workload")
@@ -559,7 +602,7 @@ def main():
     args = ap.parse_args()
     if args.only_headline:
         for flag in ("no_converge", "no_cpu_baseline", "no_fp64", "no_cholesky", "no_sparse",
-                     "no_complex", "no_batched", "no_c2_grid"):
+                     "no_complex", "no_batched", "no_c2_grid", "no_autograd"):
             setattr(args, flag, True)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -729,6 +772,9 @@ def main():
     if not args.no_c2_grid and args.workload == "c3":
         log("c2 grid: eta x tau on the 2048-orbital workload")
         result["c2_grid"] = c2_grid_bench(args, torch)
+    if not args.no_autograd and args.workload == "c3":
+        log("autograd: forward and backward on the 4096-orbital workload")
+        result["autograd_c5"] = autograd_bench(args, torch)
 
     if not args.no_batched and args.workload == "c3":
         result["batched"] = batched_bench(args)
